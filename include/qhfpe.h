@@ -1,0 +1,170 @@
+/*
+ * qhfpe.h - C-ABI of the MI355X (gfx950) propagator for the multi-state
+ * quantum hierarchical Fokker-Planck equation (MS-QHFPE) of
+ * Ikeda & Tanimura, J. Chem. Phys. (2017), arXiv:1706.09590.
+ *
+ * The library integrates the hierarchy W^(n)_jk(p, q), n = 0..N, of
+ * Sec. II, Eq. (heom) (one Drude exponential, V(q) = q, so Phi = -d/dp and
+ * Lambda^(1) = -p/m), closed at n = N by Eq. (GMFP), with classical RK4.
+ * The kinetic term uses the fifth-order upwind scheme and the potential
+ * term of Eq. (quantum-liouvillian) is evaluated through a DFT along p, as
+ * in Sec. III.  Impulsive dipole excitations and the trace Tr{mu W^(0)}
+ * give the response functions of Sec. III, Eqs. (R1) and (R3), and the
+ * spectra of Eqs. (I1), (I3) and (transient-absorption).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: QHFPE_OK (0) or a negative QHFPE_E* code; the message of
+ *    the last failure on the calling thread is qhfpe_last_error().
+ *  - Every pointer named d_* is device memory on the GPU that is current
+ *    when the handle is created; h_* is host memory.  The caller owns all
+ *    memory, including the workspace; the library allocates nothing on the
+ *    device and keeps non-owning pointers only.
+ *  - Work is enqueued on the handle's stream.  qhfpe_set_state,
+ *    qhfpe_step, qhfpe_residual and qhfpe_relax synchronise that stream
+ *    before they return (they read a result or a status flag back); the
+ *    other calls are asynchronous.
+ *  - Canonical state layout ("canon"): interleaved complex128 (re, im)
+ *    doubles, index [member][n][j][k][i][a] with n = 0..N, states j, k,
+ *    q nodes i (slowest of the grid) and p nodes a (fastest).
+ *  - Grids are half-open: q_i = q_min + i (q_max - q_min)/nq,
+ *    p_a = p_min + a (p_max - p_min)/np; p is periodic.
+ *  - Units are those of the parameters; the response functions' factors
+ *    (i/hbar)^k of Eqs. (R1), (R3) are NOT applied inside the library.
+ */
+#ifndef QHFPE_H
+#define QHFPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QHFPE_OK = 0,
+  QHFPE_EINVAL = -1,       /* null pointer, size or value out of range */
+  QHFPE_EUNSUPPORTED = -2, /* valid but not supported (np, n_states, coupling form, non-Hermitian state) */
+  QHFPE_EHIP = -3,         /* HIP runtime error; message holds hipGetErrorString */
+  QHFPE_ENONFINITE = -4,   /* NaN/Inf found in a response sample or norm */
+  QHFPE_ESTATE = -5        /* call-order error (e.g. workspace too small, mismatched handles) */
+};
+
+enum { QHFPE_FP64 = 0, QHFPE_FP32_FP64RED = 1 };
+enum { QHFPE_COMMUTATOR = 0 };
+enum { QHFPE_MAX_STATES = 3 };
+
+/* Model and discretisation.  Sec. II, Eqs. (system-Hamiltonian),
+ * (Drude-J); Sec. III (mesh).  Entries of poly/mu beyond n_states are
+ * ignored. */
+typedef struct qhfpe_params {
+  int32_t n_states;            /* electronic states, 2 or 3 */
+  int32_t nq;                  /* q nodes, >= 4 */
+  int32_t np;                  /* p nodes: 8,12,16,24,32,48,64,96,128,192 or 256 */
+  int32_t depth;               /* hierarchy depth N >= 0 (levels 0..N) */
+  int32_t batch;               /* B >= 1 independent members sharing this model */
+  int32_t precision;           /* QHFPE_FP64, or QHFPE_FP32_FP64RED (FP32 state, FP64 traces) */
+  int32_t low_temp_correction; /* 1: c0 = (m zeta hbar gamma/2) cot(beta hbar gamma/2), c_delta = m zeta/beta - c0;
+                                  0: c0 = m zeta/beta, c_delta = 0 */
+  int32_t reserved;            /* must be 0 */
+  double q_min, q_max, p_min, p_max;
+  double mass, hbar;
+  double zeta, gamma, beta;    /* Drude bath: J(w) = (m zeta/pi) w gamma^2/(gamma^2 + w^2) */
+  double dt;                   /* RK4 step */
+  /* U_jl(x) = sum_k poly[j][l][k] x^k.  Diagonal entries: any quartic.
+   * Off-diagonal entries: constant couplings only (k >= 1 must be 0);
+   * poly must be symmetric in (j, l). */
+  double poly[QHFPE_MAX_STATES][QHFPE_MAX_STATES][5];
+  double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES]; /* real symmetric Condon dipole */
+} qhfpe_params;
+
+typedef struct qhfpe_handle qhfpe_t;
+
+/* Bytes of device workspace a handle with these parameters needs.
+ * Pure host call (validates the parameters; touches no GPU). */
+int qhfpe_workspace_bytes(const qhfpe_params* params, size_t* bytes);
+
+/* Create a handle.  d_workspace: device memory of >= qhfpe_workspace_bytes,
+ * 256-byte aligned, owned by the caller and kept alive until
+ * qhfpe_destroy.  stream: a hipStream_t (NULL = default stream).  The
+ * state starts at zero with phase 0.  Parameter arrays are copied. */
+int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes,
+                 void* stream, qhfpe_t** out);
+int qhfpe_destroy(qhfpe_t* h);
+
+/* Load a canonical state.  The state is W = i^phase H with H Hermitian in
+ * (j, k) at every node (Sec. II: every hierarchy member of a Hermitian
+ * density matrix is Hermitian; each impulsive mu^x multiplies by i).
+ * member = -1 loads all B members from d_canon[B][...]; member >= 0 loads
+ * that member from d_canon[1][...] (phase must then equal the handle's).
+ * Returns QHFPE_EUNSUPPORTED when max |H_jk - conj(H_kj)| exceeds
+ * 1e-12 max |H|.  Synchronous. */
+int qhfpe_set_state(qhfpe_t* h, const double* d_canon, int32_t phase, int32_t member);
+
+/* Write the canonical state (member -1: all, into [B][...]; else one
+ * member into [1][...]), including the phase factor i^phase. */
+int qhfpe_get_state(qhfpe_t* h, double* d_canon, int32_t member);
+int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
+
+/* Initial state (Sec. III protocol; harmonic thermal Wigner function):
+ * W^(0)_00(p, q) = tanh(b)/(pi hbar) exp(-tanh(b) [p^2/(m hbar omega) + m omega q^2/hbar]),
+ * b = beta hbar omega/2, plus d_noise[i][a] (FP64 [nq][np], may be NULL);
+ * every other entry 0, phase 0, all members. */
+int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise);
+
+/* Impulsive excitation mu^x W = mu W - W mu on every level and member
+ * (Sec. III, the commutator of the Condon dipole; no i/hbar factor).
+ * Advances the phase by one. */
+int qhfpe_apply_dipole(qhfpe_t* h, int32_t mode);
+
+/* Advance nsteps RK4 steps of dt (Sec. II, Eqs. (heom), (GMFP)).
+ * If d_resp != NULL it receives, per member, the complex FP64 trace
+ * Tr{mu W^(0)} (including i^phase) at t = 0 and after every stride steps:
+ * d_resp[B][nsteps/stride + 1][2]; nsteps must be a multiple of stride.
+ * Synchronous; returns QHFPE_ENONFINITE if a sample is not finite. */
+int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp);
+
+/* Current Tr{mu W^(0)} per member, d_out[B][2] (FP64, including i^phase). */
+int qhfpe_response(qhfpe_t* h, double* d_out);
+
+/* Test hook: state <- L(state), the right-hand side of Eq. (heom)/(GMFP),
+ * with no time step. */
+int qhfpe_apply_rhs(qhfpe_t* h);
+
+/* h_out[B][2] (host): ||L W||_2 and ||W||_2 per member over the whole
+ * hierarchy (canonical complex entries).  Synchronous. */
+int qhfpe_residual(qhfpe_t* h, double* h_out);
+
+/* Relax towards the correlated thermal equilibrium of the full hierarchy
+ * (Sec. III protocol): step in chunks of check_every until every member has
+ * ||L W|| / ||W|| < tol or max_steps is reached.  Outputs may be NULL.
+ * Synchronous. */
+int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every,
+                int64_t* h_steps_done, double* h_residual);
+
+/* Copy count members src[src_member..] -> dst[dst_member..] device to
+ * device (multi-time protocol of Sec. III).  Both handles must share
+ * n_states, nq, np, depth and precision; dst takes src's phase. */
+int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst,
+                       int32_t dst_member, int32_t count);
+
+/* Sec. III, Eq. (I1) (and Eq. (transient-absorption) for an R3(t, T, 0)
+ * series): d_out[w] = omega_w Im sum_s c_s dt exp(i omega_w s dt) R[s],
+ * trapezoid weights c_s, no window.  d_series: complex [n][2]. */
+int qhfpe_spectrum_abs(const double* d_series, int64_t n, double dt, const double* d_omega,
+                       int32_t n_omega, double* d_out, void* stream);
+
+/* Sec. III, Eqs. (I3), (nonreph), (reph) for one waiting time:
+ * d_out[w3][w1] = Im sum_{t1,t3} c c dt1 dt3 e^{i w3 t3} (e^{i w1 t1} + e^{-i w1 t1}) R3[t1][t3].
+ * d_r3: complex [n1][n3][2]; d_work: >= n1 * n_w3 * 2 doubles of scratch. */
+int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3,
+                        const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3,
+                        double* d_work, double* d_out, void* stream);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* qhfpe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QHFPE_H */

@@ -1,0 +1,520 @@
+// Host side of the MS-QHFPE C-ABI: parameter validation, workspace layout,
+// launch sequencing of the RK4 stages, response finalisation and errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qhfpe.h"
+#include "qhfpe_internal.hpp"
+
+using namespace qhfpe;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(QHFPE_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t elem = 0;
+  long long member_elems = 0, level_elems = 0, comp_elems = 0;
+  size_t state_bytes = 0;
+  size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
+  size_t total = 0;
+  size_t red_count = 0;
+  int tq = 0, ntiles = 0;
+};
+
+int validate(const qhfpe_params* p) {
+  if (!p) return fail(QHFPE_EINVAL, "params is NULL");
+  if (p->n_states != 2 && p->n_states != 3)
+    return fail(QHFPE_EUNSUPPORTED, "n_states must be 2 or 3 (got %d)", p->n_states);
+  if (p->nq < 4) return fail(QHFPE_EINVAL, "nq must be >= 4 (got %d)", p->nq);
+  if (!find_plan(p->np))
+    return fail(QHFPE_EUNSUPPORTED, "np=%d not supported (8,12,16,24,32,48,64,96,128,192,256)", p->np);
+  if (p->depth < 0 || p->depth > 64) return fail(QHFPE_EINVAL, "depth must be in [0, 64] (got %d)", p->depth);
+  if (p->batch < 1) return fail(QHFPE_EINVAL, "batch must be >= 1 (got %d)", p->batch);
+  if (p->precision != QHFPE_FP64 && p->precision != QHFPE_FP32_FP64RED)
+    return fail(QHFPE_EINVAL, "unknown precision %d", p->precision);
+  if (p->reserved != 0) return fail(QHFPE_EINVAL, "reserved must be 0");
+  if (!(p->q_max > p->q_min) || !(p->p_max > p->p_min)) return fail(QHFPE_EINVAL, "empty q or p range");
+  if (!(p->mass > 0) || !(p->hbar > 0)) return fail(QHFPE_EINVAL, "mass and hbar must be > 0");
+  if (!(p->zeta >= 0) || !(p->gamma > 0) || !(p->beta > 0))
+    return fail(QHFPE_EINVAL, "need zeta >= 0, gamma > 0, beta > 0");
+  if (p->low_temp_correction && !(p->beta * p->hbar * p->gamma < 2.0 * M_PI))
+    return fail(QHFPE_EUNSUPPORTED, "low-temperature correction needs beta hbar gamma < 2 pi");
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(QHFPE_EINVAL, "dt must be finite and > 0");
+  const int ns = p->n_states;
+  for (int j = 0; j < ns; ++j)
+    for (int l = 0; l < ns; ++l) {
+      for (int k = 0; k < 5; ++k) {
+        if (!std::isfinite(p->poly[j][l][k])) return fail(QHFPE_EINVAL, "poly has a non-finite entry");
+        if (p->poly[j][l][k] != p->poly[l][j][k]) return fail(QHFPE_EINVAL, "poly must be symmetric");
+        if (j != l && k >= 1 && p->poly[j][l][k] != 0.0)
+          return fail(QHFPE_EUNSUPPORTED, "off-diagonal couplings must be constant (poly[%d][%d][%d] != 0)", j, l, k);
+      }
+      if (!std::isfinite(p->mu[j][l]) || p->mu[j][l] != p->mu[l][j])
+        return fail(QHFPE_EINVAL, "mu must be finite and symmetric");
+    }
+  const long double elems = (long double)p->batch * (p->depth + 1) * ns * ns * p->nq * p->np;
+  if (elems > 4.0e11L) return fail(QHFPE_EINVAL, "state too large");
+  return QHFPE_OK;
+}
+
+Layout make_layout(const qhfpe_params* p) {
+  Layout L;
+  const Plan* pl = find_plan(p->np);
+  const int nc = p->n_states * p->n_states;
+  L.elem = (p->precision == QHFPE_FP64) ? 8 : 4;
+  L.comp_elems = (long long)p->nq * p->np;
+  L.level_elems = L.comp_elems * nc;
+  L.member_elems = L.level_elems * (p->depth + 1);
+  L.state_bytes = align_up((size_t)L.member_elems * p->batch * L.elem);
+  L.tq = pl->tq;
+  L.ntiles = (p->nq + pl->tq - 1) / pl->tq;
+  const long long cells = (long long)(p->depth + 1) * p->nq * p->np;
+  const long long pack_blocks = (cells + kBlock - 1) / kBlock;
+  L.red_count = (size_t)p->batch * (size_t)std::max<long long>(2 * pack_blocks, 1024);
+  size_t off = 0;
+  L.off_y = off;
+  off += L.state_bytes;
+  L.off_va = off;
+  off += L.state_bytes;
+  L.off_vb = off;
+  off += L.state_bytes;
+  L.off_partials = off;
+  off += align_up((size_t)p->batch * kRespSlots * L.ntiles * sizeof(double));
+  L.off_red = off;
+  off += align_up(L.red_count * sizeof(double));
+  L.off_tw = off;
+  off += align_up((size_t)p->np * 2 * L.elem);
+  L.off_flag = off;
+  off += kAlign;
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct qhfpe_handle {
+  qhfpe_params p;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int phase = 0;
+  int ns = 0, nc = 0, levels = 0;
+  double r0 = 0, c0 = 0, cdelta = 0, dq = 0, dp = 0, dr = 0;
+
+  void* y() const { return ws + L.off_y; }
+  void* va() const { return ws + L.off_va; }
+  void* vb() const { return ws + L.off_vb; }
+  double* partials() const { return reinterpret_cast<double*>(ws + L.off_partials); }
+  double* red() const { return reinterpret_cast<double*>(ws + L.off_red); }
+  void* twiddle() const { return ws + L.off_tw; }
+  int* flag() const { return reinterpret_cast<int*>(ws + L.off_flag); }
+
+  GridDesc grid() const {
+    GridDesc g;
+    g.ns = ns;
+    g.nq = p.nq;
+    g.np = p.np;
+    g.levels = levels;
+    g.batch = p.batch;
+    g.precision = p.precision;
+    g.member_stride = L.member_elems;
+    g.level_stride = L.level_elems;
+    g.comp_stride = L.comp_elems;
+    return g;
+  }
+
+  StageArgs stage_args(const void* v, const void* yb, void* out, double coef) const {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.y = yb;
+    a.out = out;
+    a.partials = nullptr;
+    a.twiddle = twiddle();
+    a.slot = 0;
+    a.nq = p.nq;
+    a.depth = p.depth;
+    a.ntiles = L.ntiles;
+    a.member_stride = L.member_elems;
+    a.level_stride = L.level_elems;
+    a.comp_stride = L.comp_elems;
+    a.coef = coef;
+    a.dq = dq;
+    a.dp = dp;
+    a.dr = dr;
+    a.q0 = p.q_min;
+    a.p0 = p.p_min;
+    a.qlo = p.q_min;
+    a.qhi = p.q_min + (p.nq - 1) * dq;
+    a.inv_mass = 1.0 / p.mass;
+    a.inv_hbar = 1.0 / p.hbar;
+    a.zeta = r0 / p.mass;
+    a.gamma = p.gamma;
+    a.c0 = c0;
+    a.cdelta = cdelta;
+    for (int j = 0; j < ns; ++j) {
+      for (int k = 0; k < 5; ++k) a.poly[j][k] = p.poly[j][j][k];
+      for (int l = 0; l < ns; ++l) {
+        a.coup[j][l] = (j == l) ? 0.0 : p.poly[j][l][0] / p.hbar;
+        a.mu[j][l] = p.mu[j][l];
+      }
+    }
+    return a;
+  }
+
+  hipError_t launch(const StageArgs& a) const {
+    const int nblocks = L.ntiles * levels * p.batch;
+    if (p.precision == QHFPE_FP64)
+      return ns == 2 ? launch_stage_f64_ns2(p.np, a, nblocks, stream) : launch_stage_f64_ns3(p.np, a, nblocks, stream);
+    return ns == 2 ? launch_stage_f32_ns2(p.np, a, nblocks, stream) : launch_stage_f32_ns3(p.np, a, nblocks, stream);
+  }
+};
+
+namespace {
+
+int check_handle(const qhfpe_t* h) {
+  if (!h) return fail(QHFPE_EINVAL, "handle is NULL");
+  return QHFPE_OK;
+}
+
+// partial sums of the level-0 trace of y into slot, then (optionally) finalise
+int trace_into(qhfpe_t* h, int slot) {
+  HIP_TRY(launch_trace_partials(h->grid(), h->y(), h->p.mu, h->L.tq, h->L.ntiles, h->partials(), slot, h->stream));
+  return QHFPE_OK;
+}
+
+int finalize(qhfpe_t* h, int nslots, double* resp, long long resp_stride, long long offset) {
+  HIP_TRY(launch_finalize(h->p.batch, h->L.ntiles, nslots, h->partials(), h->dq * h->dp, h->phase, resp,
+                          resp_stride, offset, h->flag(), h->stream));
+  return QHFPE_OK;
+}
+
+int read_flag(qhfpe_t* h, int* value) {
+  HIP_TRY(hipMemcpyAsync(value, h->flag(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return QHFPE_OK;
+}
+
+// ||buf||_2 per member into out[b] (host)
+int norms(qhfpe_t* h, const void* buf, std::vector<double>& out) {
+  int nb = 0;
+  HIP_TRY(launch_norm_partials(h->grid(), buf, h->red(), &nb, h->stream));
+  std::vector<double> host((size_t)nb * h->p.batch);
+  HIP_TRY(hipMemcpyAsync(host.data(), h->red(), host.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  out.assign(h->p.batch, 0.0);
+  for (int b = 0; b < h->p.batch; ++b) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += host[(size_t)b * nb + i];
+    out[b] = std::sqrt(s);
+  }
+  return QHFPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qhfpe_last_error(void) { return g_err.c_str(); }
+
+int qhfpe_workspace_bytes(const qhfpe_params* params, size_t* bytes) {
+  if (!bytes) return fail(QHFPE_EINVAL, "bytes is NULL");
+  int rc = validate(params);
+  if (rc) return rc;
+  *bytes = make_layout(params).total;
+  return QHFPE_OK;
+}
+
+int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, void* stream, qhfpe_t** out) {
+  if (!out) return fail(QHFPE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  if (!d_workspace) return fail(QHFPE_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return fail(QHFPE_EINVAL, "workspace must be 256-byte aligned");
+  Layout L = make_layout(params);
+  if (bytes < L.total) return fail(QHFPE_ESTATE, "workspace too small: %zu < %zu bytes", bytes, L.total);
+  qhfpe_t* h = new (std::nothrow) qhfpe_handle();
+  if (!h) return fail(QHFPE_EINVAL, "out of host memory");
+  h->p = *params;
+  h->L = L;
+  h->ws = static_cast<char*>(d_workspace);
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ns = params->n_states;
+  h->nc = h->ns * h->ns;
+  h->levels = params->depth + 1;
+  h->dq = (params->q_max - params->q_min) / params->nq;
+  h->dp = (params->p_max - params->p_min) / params->np;
+  h->dr = 2.0 * M_PI * params->hbar / (params->np * h->dp);
+  h->r0 = params->mass * params->zeta;
+  if (params->low_temp_correction) {
+    const double x = 0.5 * params->beta * params->hbar * params->gamma;
+    h->c0 = 0.5 * params->mass * params->zeta * params->hbar * params->gamma * std::cos(x) / std::sin(x);
+    h->cdelta = params->mass * params->zeta / params->beta - h->c0;
+  } else {
+    h->c0 = params->mass * params->zeta / params->beta;
+    h->cdelta = 0.0;
+  }
+  // twiddles exp(+2 pi i j / np), computed in FP64 and rounded once
+  const int np = params->np;
+  std::vector<double> tw64(2 * (size_t)np);
+  std::vector<float> tw32(2 * (size_t)np);
+  for (int j = 0; j < np; ++j) {
+    const double ang = 2.0 * M_PI * (double)j / (double)np;
+    tw64[2 * j] = std::cos(ang);
+    tw64[2 * j + 1] = std::sin(ang);
+    tw32[2 * j] = (float)tw64[2 * j];
+    tw32[2 * j + 1] = (float)tw64[2 * j + 1];
+  }
+  const void* src = (params->precision == QHFPE_FP64) ? (const void*)tw64.data() : (const void*)tw32.data();
+  hipError_t e = hipMemcpyAsync(h->twiddle(), src, (size_t)np * 2 * L.elem, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->y(), 0, 3 * L.state_bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->flag(), 0, sizeof(int), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(QHFPE_EHIP, "create: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return QHFPE_OK;
+}
+
+int qhfpe_destroy(qhfpe_t* h) {
+  if (!h) return QHFPE_OK;
+  delete h;
+  return QHFPE_OK;
+}
+
+int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase) {
+  if (int rc = check_handle(h)) return rc;
+  if (!phase) return fail(QHFPE_EINVAL, "phase is NULL");
+  *phase = h->phase;
+  return QHFPE_OK;
+}
+
+int qhfpe_set_state(qhfpe_t* h, const double* d_canon, int32_t phase, int32_t member) {
+  if (int rc = check_handle(h)) return rc;
+  if (!d_canon) return fail(QHFPE_EINVAL, "d_canon is NULL");
+  if (phase < 0 || phase > 3) return fail(QHFPE_EINVAL, "phase must be 0..3");
+  if (member < -1 || member >= h->p.batch) return fail(QHFPE_EINVAL, "member out of range");
+  if (member >= 0 && phase != h->phase)
+    return fail(QHFPE_ESTATE, "single-member load with phase %d into a handle of phase %d", phase, h->phase);
+  const int first = member < 0 ? 0 : member;
+  const int count = member < 0 ? h->p.batch : 1;
+  int nblk = 0;
+  // convert into the scratch buffer first; commit only a Hermitian state
+  HIP_TRY(launch_pack(h->grid(), d_canon, phase, h->va(), first, count, h->red(), &nblk, h->stream));
+  std::vector<double> red((size_t)nblk * count * 2);
+  HIP_TRY(hipMemcpyAsync(red.data(), h->red(), red.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double dev = 0.0, mag = 0.0;
+  for (size_t i = 0; i < red.size(); i += 2) {
+    dev = std::max(dev, red[i]);
+    mag = std::max(mag, red[i + 1]);
+  }
+  if (!std::isfinite(dev) || !std::isfinite(mag)) return fail(QHFPE_ENONFINITE, "state has NaN/Inf entries");
+  if (dev > 1e-12 * std::max(mag, 1e-300))
+    return fail(QHFPE_EUNSUPPORTED, "state is not i^%d times a Hermitian matrix (deviation %.3e of max %.3e)",
+                phase, dev, mag);
+  const size_t mb = (size_t)h->L.member_elems * h->L.elem;
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(h->y()) + first * mb, static_cast<char*>(h->va()) + first * mb,
+                         count * mb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->phase = phase;
+  return QHFPE_OK;
+}
+
+int qhfpe_get_state(qhfpe_t* h, double* d_canon, int32_t member) {
+  if (int rc = check_handle(h)) return rc;
+  if (!d_canon) return fail(QHFPE_EINVAL, "d_canon is NULL");
+  if (member < -1 || member >= h->p.batch) return fail(QHFPE_EINVAL, "member out of range");
+  const int first = member < 0 ? 0 : member;
+  const int count = member < 0 ? h->p.batch : 1;
+  HIP_TRY(launch_unpack(h->grid(), h->y(), h->phase, d_canon, first, count, h->stream));
+  return QHFPE_OK;
+}
+
+int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise) {
+  if (int rc = check_handle(h)) return rc;
+  if (!(omega > 0) || !std::isfinite(omega)) return fail(QHFPE_EINVAL, "omega must be finite and > 0");
+  const double tb = std::tanh(0.5 * h->p.beta * h->p.hbar * omega);
+  HIP_TRY(launch_thermal(h->grid(), h->y(), h->p.q_min, h->dq, h->p.p_min, h->dp, tb, omega, h->p.mass,
+                         h->p.hbar, d_noise, h->stream));
+  h->phase = 0;
+  return QHFPE_OK;
+}
+
+int qhfpe_apply_dipole(qhfpe_t* h, int32_t mode) {
+  if (int rc = check_handle(h)) return rc;
+  if (mode != QHFPE_COMMUTATOR) return fail(QHFPE_EUNSUPPORTED, "only QHFPE_COMMUTATOR is supported");
+  HIP_TRY(launch_dipole(h->grid(), h->y(), h->p.mu, h->stream));
+  h->phase = (h->phase + 1) & 3;
+  return QHFPE_OK;
+}
+
+int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
+  if (int rc = check_handle(h)) return rc;
+  if (nsteps < 0) return fail(QHFPE_EINVAL, "nsteps must be >= 0");
+  if (stride < 1) return fail(QHFPE_EINVAL, "stride must be >= 1");
+  if (d_resp && nsteps % stride) return fail(QHFPE_EINVAL, "nsteps must be a multiple of stride");
+  const double dt = h->p.dt;
+  const long long nsamples = d_resp ? nsteps / stride + 1 : 0;
+  HIP_TRY(hipMemsetAsync(h->flag(), 0, sizeof(int), h->stream));
+  int slot = 0;
+  long long base = 0;
+  if (d_resp) {
+    if (int rc = trace_into(h, 0)) return rc;
+    slot = 1;
+  }
+  StageArgs s1 = h->stage_args(h->y(), h->y(), h->va(), 0.25 * dt);
+  StageArgs s2 = h->stage_args(h->va(), h->y(), h->vb(), dt / 3.0);
+  StageArgs s3 = h->stage_args(h->vb(), h->y(), h->va(), 0.5 * dt);
+  StageArgs s4 = h->stage_args(h->va(), h->y(), h->y(), dt);
+  for (int64_t s = 1; s <= nsteps; ++s) {
+    HIP_TRY(h->launch(s1));
+    HIP_TRY(h->launch(s2));
+    HIP_TRY(h->launch(s3));
+    const bool sample = d_resp && (s % stride == 0);
+    s4.partials = sample ? h->partials() : nullptr;
+    s4.slot = slot;
+    HIP_TRY(h->launch(s4));
+    if (sample && ++slot == kRespSlots) {
+      if (int rc = finalize(h, slot, d_resp, nsamples * 2, base)) return rc;
+      base += slot;
+      slot = 0;
+    }
+  }
+  if (d_resp && slot > 0) {
+    if (int rc = finalize(h, slot, d_resp, nsamples * 2, base)) return rc;
+  }
+  if (!d_resp) {
+    if (int rc = trace_into(h, 0)) return rc;
+    if (int rc = finalize(h, 1, nullptr, 0, 0)) return rc;
+  }
+  int flag = 0;
+  if (int rc = read_flag(h, &flag)) return rc;
+  if (flag) return fail(QHFPE_ENONFINITE, "non-finite trace during propagation (dt too large?)");
+  return QHFPE_OK;
+}
+
+int qhfpe_response(qhfpe_t* h, double* d_out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!d_out) return fail(QHFPE_EINVAL, "d_out is NULL");
+  if (int rc = trace_into(h, 0)) return rc;
+  return finalize(h, 1, d_out, 2, 0);
+}
+
+int qhfpe_apply_rhs(qhfpe_t* h) {
+  if (int rc = check_handle(h)) return rc;
+  StageArgs a = h->stage_args(h->y(), nullptr, h->va(), 1.0);
+  HIP_TRY(h->launch(a));
+  HIP_TRY(hipMemcpyAsync(h->y(), h->va(), (size_t)h->L.member_elems * h->p.batch * h->L.elem,
+                         hipMemcpyDeviceToDevice, h->stream));
+  return QHFPE_OK;
+}
+
+int qhfpe_residual(qhfpe_t* h, double* h_out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h_out) return fail(QHFPE_EINVAL, "h_out is NULL");
+  StageArgs a = h->stage_args(h->y(), nullptr, h->va(), 1.0);
+  HIP_TRY(h->launch(a));
+  std::vector<double> nl, nw;
+  if (int rc = norms(h, h->va(), nl)) return rc;
+  if (int rc = norms(h, h->y(), nw)) return rc;
+  for (int b = 0; b < h->p.batch; ++b) {
+    h_out[2 * b] = nl[b];
+    h_out[2 * b + 1] = nw[b];
+  }
+  return QHFPE_OK;
+}
+
+int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every, int64_t* h_steps_done,
+                double* h_residual) {
+  if (int rc = check_handle(h)) return rc;
+  if (!(tol > 0) || max_steps < 0 || check_every < 1) return fail(QHFPE_EINVAL, "bad relax arguments");
+  std::vector<double> r(2 * (size_t)h->p.batch);
+  int64_t done = 0;
+  double worst = INFINITY;
+  while (true) {
+    if (int rc = qhfpe_residual(h, r.data())) return rc;
+    worst = 0.0;
+    for (int b = 0; b < h->p.batch; ++b) {
+      const double q = r[2 * b] / std::max(r[2 * b + 1], 1e-300);
+      if (!std::isfinite(q)) return fail(QHFPE_ENONFINITE, "non-finite residual during relaxation");
+      worst = std::max(worst, q);
+    }
+    if (worst < tol || done >= max_steps) break;
+    const int64_t n = std::min<int64_t>(check_every, max_steps - done);
+    if (int rc = qhfpe_step(h, n, 1, nullptr)) return rc;
+    done += n;
+  }
+  if (h_steps_done) *h_steps_done = done;
+  if (h_residual) *h_residual = worst;
+  return QHFPE_OK;
+}
+
+int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int32_t dst_member, int32_t count) {
+  if (!src || !dst) return fail(QHFPE_EINVAL, "handle is NULL");
+  if (src->ns != dst->ns || src->p.nq != dst->p.nq || src->p.np != dst->p.np || src->p.depth != dst->p.depth ||
+      src->p.precision != dst->p.precision)
+    return fail(QHFPE_ESTATE, "handles differ in n_states, grid, depth or precision");
+  if (count < 0 || src_member < 0 || dst_member < 0 || src_member + count > src->p.batch ||
+      dst_member + count > dst->p.batch)
+    return fail(QHFPE_EINVAL, "member range out of bounds");
+  if (count == 0) return QHFPE_OK;
+  const size_t mb = (size_t)src->L.member_elems * src->L.elem;
+  if (src->stream != dst->stream) HIP_TRY(hipStreamSynchronize(src->stream));
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst->y()) + dst_member * mb,
+                         static_cast<const char*>(src->y()) + src_member * mb, count * mb,
+                         hipMemcpyDeviceToDevice, dst->stream));
+  dst->phase = src->phase;
+  return QHFPE_OK;
+}
+
+int qhfpe_spectrum_abs(const double* d_series, int64_t n, double dt, const double* d_omega, int32_t n_omega,
+                       double* d_out, void* stream) {
+  if (!d_series || !d_omega || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
+  if (n < 1 || n_omega < 1 || !(dt > 0)) return fail(QHFPE_EINVAL, "bad sizes");
+  HIP_TRY(launch_spectrum_abs(d_series, n, dt, d_omega, n_omega, d_out, static_cast<hipStream_t>(stream)));
+  return QHFPE_OK;
+}
+
+int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3, const double* d_w1,
+                        int32_t n_w1, const double* d_w3, int32_t n_w3, double* d_work, double* d_out,
+                        void* stream) {
+  if (!d_r3 || !d_w1 || !d_w3 || !d_work || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
+  if (n1 < 1 || n3 < 1 || n_w1 < 1 || n_w3 < 1 || !(dt1 > 0) || !(dt3 > 0)) return fail(QHFPE_EINVAL, "bad sizes");
+  HIP_TRY(launch_spectrum_corr(d_r3, n1, n3, dt1, dt3, d_w1, n_w1, d_w3, n_w3, d_work, d_out,
+                               static_cast<hipStream_t>(stream)));
+  return QHFPE_OK;
+}
+
+}  // extern "C"

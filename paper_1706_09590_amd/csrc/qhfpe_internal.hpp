@@ -1,0 +1,94 @@
+// Internal declarations shared by the host API and the kernels of the
+// MS-QHFPE library.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "qhfpe.h"
+
+namespace qhfpe {
+
+constexpr int kBlock = 256;        // threads per workgroup of every grid kernel
+constexpr int kRespSlots = 256;    // response samples buffered between finalisations
+
+// Two-pass FFT plan along p (np = n1 * n2, n1 even) and the q-tile width of
+// one stage workgroup, for every supported np.
+struct Plan {
+  int np, n1, n2, tq;
+};
+constexpr Plan kPlans[] = {
+    {8, 4, 2, 16},    {12, 4, 3, 16},  {16, 4, 4, 16},   {24, 6, 4, 16},
+    {32, 8, 4, 16},   {48, 8, 6, 16},  {64, 8, 8, 16},   {96, 12, 8, 8},
+    {128, 16, 8, 8},  {192, 16, 12, 4}, {256, 16, 16, 4},
+};
+inline const Plan* find_plan(int np) {
+  for (const Plan& p : kPlans)
+    if (p.np == np) return &p;
+  return nullptr;
+}
+
+// Arguments of the fused RK-stage kernel (passed by value).
+struct StageArgs {
+  const void* v;        // stage input, packed [B][N+1][nc][nq][np]
+  const void* y;        // RK4 base state (nullptr: treated as zero)
+  void* out;            // y + coef * L v
+  double* partials;     // [B][kRespSlots][ntiles] level-0 trace partials, or nullptr
+  const void* twiddle;  // np complex entries exp(+2 pi i j/np) in the state precision
+  int slot;
+  int nq;
+  int depth;
+  int ntiles;
+  long long member_stride;  // elements per member
+  long long level_stride;   // elements per level
+  long long comp_stride;    // elements per packed component (nq * np)
+  double coef;
+  double dq, dp, dr, q0, p0, qlo, qhi;
+  double inv_mass, inv_hbar;
+  double zeta, gamma, c0, cdelta;
+  double poly[QHFPE_MAX_STATES][5];                    // diagonal surfaces
+  double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];     // off-diagonal couplings / hbar
+  double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
+};
+
+// Host launchers (one translation unit per precision and state count).
+hipError_t launch_stage_f64_ns2(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f64_ns3(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f32_ns2(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f32_ns3(int np, const StageArgs& a, int nblocks, hipStream_t s);
+
+// Pointwise and reduction kernels (aux_kernels.hip).
+struct DipoleMu {
+  double m[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
+};
+
+struct GridDesc {
+  int ns, nq, np, levels, batch, precision;
+  long long member_stride, level_stride, comp_stride;
+};
+
+hipError_t launch_pack(const GridDesc& g, const double* canon, int phase, void* packed,
+                       int member_offset, int nmembers, double* red, int* nred_blocks,
+                       hipStream_t s);
+hipError_t launch_unpack(const GridDesc& g, const void* packed, int phase, double* canon,
+                         int member_offset, int nmembers, hipStream_t s);
+hipError_t launch_dipole(const GridDesc& g, void* packed, const double mu[3][3], hipStream_t s);
+hipError_t launch_thermal(const GridDesc& g, void* packed, double q0, double dq, double p0,
+                          double dp, double tanh_b, double omega, double mass, double hbar,
+                          const double* noise, hipStream_t s);
+hipError_t launch_trace_partials(const GridDesc& g, const void* packed, const double mu[3][3],
+                                 int tq, int ntiles, double* partials, int slot, hipStream_t s);
+hipError_t launch_finalize(int batch, int ntiles, int nslots, const double* partials,
+                           double scale, int phase, double* resp, long long resp_stride,
+                           long long resp_offset, int* flag, hipStream_t s);
+hipError_t launch_norm_partials(const GridDesc& g, const void* packed, double* red,
+                                int* nblocks_per_member, hipStream_t s);
+hipError_t launch_spectrum_abs(const double* series, long long n, double dt, const double* omega,
+                               int n_omega, double* out, hipStream_t s);
+hipError_t launch_spectrum_corr(const double* r3, int n1, int n3, double dt1, double dt3,
+                                const double* w1, int nw1, const double* w3, int nw3,
+                                double* work, double* out, hipStream_t s);
+
+}  // namespace qhfpe

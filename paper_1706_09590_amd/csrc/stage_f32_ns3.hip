@@ -1,0 +1,8 @@
+// Instantiations of the fused RK stage for float state, 3 electronic states.
+#include "stage_kernel.hpp"
+
+namespace qhfpe {
+hipError_t launch_stage_f32_ns3(int np, const StageArgs& a, int nblocks, hipStream_t s) {
+  return launch_stage<float, 3>(np, a, nblocks, s);
+}
+}  // namespace qhfpe

@@ -1,0 +1,270 @@
+"""Thin Python binding of the qhfpe C-ABI (include/qhfpe.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch provides device memory (the workspace and the state /
+response buffers) and the stream.  There is no fallback: if libqhfpe.so is
+missing, importing the library raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqhfpe.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "qhfpe.h")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32_FP64RED = 0, 1
+COMMUTATOR = 0
+MAX_STATES = 3
+
+_c_int = ctypes.c_int
+_c_i32 = ctypes.c_int32
+_c_i64 = ctypes.c_int64
+_c_dbl = ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_states", _c_i32), ("nq", _c_i32), ("np", _c_i32), ("depth", _c_i32),
+        ("batch", _c_i32), ("precision", _c_i32), ("low_temp_correction", _c_i32),
+        ("reserved", _c_i32),
+        ("q_min", _c_dbl), ("q_max", _c_dbl), ("p_min", _c_dbl), ("p_max", _c_dbl),
+        ("mass", _c_dbl), ("hbar", _c_dbl),
+        ("zeta", _c_dbl), ("gamma", _c_dbl), ("beta", _c_dbl),
+        ("dt", _c_dbl),
+        ("poly", _c_dbl * 5 * MAX_STATES * MAX_STATES),
+        ("mu", _c_dbl * MAX_STATES * MAX_STATES),
+    ]
+
+
+class QHFPEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qhfpe error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libqhfpe.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Params)
+    sig = {
+        "qhfpe_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], _c_int),
+        "qhfpe_create": ([P, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], _c_int),
+        "qhfpe_destroy": ([_vp], _c_int),
+        "qhfpe_set_state": ([_vp, _vp, _c_i32, _c_i32], _c_int),
+        "qhfpe_get_state": ([_vp, _vp, _c_i32], _c_int),
+        "qhfpe_get_phase": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
+        "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
+        "qhfpe_apply_dipole": ([_vp, _c_i32], _c_int),
+        "qhfpe_step": ([_vp, _c_i64, _c_i32, _vp], _c_int),
+        "qhfpe_response": ([_vp, _vp], _c_int),
+        "qhfpe_apply_rhs": ([_vp], _c_int),
+        "qhfpe_residual": ([_vp, ctypes.POINTER(_c_dbl)], _c_int),
+        "qhfpe_relax": ([_vp, _c_dbl, _c_i64, _c_i32, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_dbl)], _c_int),
+        "qhfpe_copy_members": ([_vp, _c_i32, _vp, _c_i32, _c_i32], _c_int),
+        "qhfpe_spectrum_abs": ([_vp, _c_i64, _c_dbl, _vp, _c_i32, _vp, _vp], _c_int),
+        "qhfpe_spectrum_corr": ([_vp, _c_i32, _c_i32, _c_dbl, _c_dbl, _vp, _c_i32, _vp, _c_i32, _vp, _vp, _vp],
+                                _c_int),
+        "qhfpe_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list[str]:
+    """Names of the entry points declared in include/qhfpe.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"\b(qhfpe_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise QHFPEError(rc, lib().qhfpe_last_error().decode())
+
+
+def make_params(model: dict, batch: int = 1, precision: str = "fp64") -> Params:
+    p = Params()
+    p.n_states = int(model["n_states"])
+    p.nq = int(model["nq"])
+    p.np = int(model["np"])
+    p.depth = int(model["depth"])
+    p.batch = int(batch)
+    p.precision = {"fp64": FP64, "fp32": FP32_FP64RED}[precision]
+    p.low_temp_correction = int(bool(model.get("low_temp_correction", True)))
+    p.reserved = 0
+    for k in ("q_min", "q_max", "p_min", "p_max", "zeta", "gamma", "beta", "dt"):
+        setattr(p, k, float(model[k]))
+    p.mass = float(model.get("mass", 1.0))
+    p.hbar = float(model.get("hbar", 1.0))
+    ns = p.n_states
+    poly = np.zeros((MAX_STATES, MAX_STATES, 5))
+    poly[:ns, :ns, :] = np.asarray(model["poly"], dtype=np.float64)[:ns, :ns, :5]
+    mu = np.zeros((MAX_STATES, MAX_STATES))
+    mu[:ns, :ns] = np.asarray(model["mu"], dtype=np.float64)
+    for j in range(MAX_STATES):
+        for l in range(MAX_STATES):
+            p.mu[j][l] = mu[j, l]
+            for k in range(5):
+                p.poly[j][l][k] = poly[j, l, k]
+    return p
+
+
+def workspace_bytes(model: dict, batch: int = 1, precision: str = "fp64") -> int:
+    p = make_params(model, batch, precision)
+    n = ctypes.c_size_t(0)
+    _check(lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _ptr(t) -> int:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Propagator:
+    """One qhfpe handle: a batch of propagations of one model on one GPU."""
+
+    def __init__(self, model: dict, batch: int = 1, precision: str = "fp64", device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.model = dict(model)
+        self.batch = int(batch)
+        self.precision = precision
+        self.device = torch.device(device if device is not None else "cuda")
+        self.params = make_params(model, batch, precision)
+        nbytes = workspace_bytes(model, batch, precision)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        h = ctypes.c_void_p()
+        _check(lib().qhfpe_create(ctypes.byref(self.params), _ptr(self.workspace), nbytes,
+                                  ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.shape = (self.model["depth"] + 1, self.model["n_states"], self.model["n_states"],
+                      self.model["nq"], self.model["np"])
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().qhfpe_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state ---------------------------------------------------------------
+    def set_state(self, W, phase: int = 0, member: int = -1):
+        t = self.torch
+        W = t.as_tensor(W, dtype=t.complex128, device=self.device).contiguous()
+        self._keep = W
+        _check(lib().qhfpe_set_state(self.handle, _ptr(W), int(phase), int(member)))
+
+    def get_state(self, member: int = -1):
+        t = self.torch
+        n = self.batch if member < 0 else 1
+        out = t.empty((n,) + self.shape, dtype=t.complex128, device=self.device)
+        _check(lib().qhfpe_get_state(self.handle, _ptr(out), int(member)))
+        return out
+
+    @property
+    def phase(self) -> int:
+        v = _c_i32(0)
+        _check(lib().qhfpe_get_phase(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    def init_thermal(self, omega: float, noise=None):
+        t = self.torch
+        ptr = None
+        if noise is not None:
+            noise = t.as_tensor(noise, dtype=t.float64, device=self.device).contiguous()
+            self._noise = noise
+            ptr = _ptr(noise)
+        _check(lib().qhfpe_init_thermal(self.handle, float(omega), ptr))
+
+    # -- dynamics ------------------------------------------------------------
+    def apply_dipole(self):
+        _check(lib().qhfpe_apply_dipole(self.handle, COMMUTATOR))
+
+    def step(self, nsteps: int, stride: int = 1, record: bool = True, out=None):
+        t = self.torch
+        if not record:
+            _check(lib().qhfpe_step(self.handle, int(nsteps), int(stride), None))
+            return None
+        n = nsteps // stride + 1
+        if out is None:
+            out = t.empty((self.batch, n), dtype=t.complex128, device=self.device)
+        _check(lib().qhfpe_step(self.handle, int(nsteps), int(stride), _ptr(out)))
+        return out
+
+    def response(self):
+        t = self.torch
+        out = t.empty((self.batch,), dtype=t.complex128, device=self.device)
+        _check(lib().qhfpe_response(self.handle, _ptr(out)))
+        return out
+
+    def apply_rhs(self):
+        _check(lib().qhfpe_apply_rhs(self.handle))
+
+    def residual(self) -> np.ndarray:
+        out = (_c_dbl * (2 * self.batch))()
+        _check(lib().qhfpe_residual(self.handle, out))
+        return np.array(out[:]).reshape(self.batch, 2)
+
+    def relax(self, tol: float, max_steps: int, check_every: int = 100):
+        steps = _c_i64(0)
+        res = _c_dbl(0.0)
+        _check(lib().qhfpe_relax(self.handle, float(tol), int(max_steps), int(check_every),
+                                 ctypes.byref(steps), ctypes.byref(res)))
+        return int(steps.value), float(res.value)
+
+    def copy_members_from(self, src: "Propagator", src_member: int, dst_member: int, count: int):
+        _check(lib().qhfpe_copy_members(src.handle, int(src_member), self.handle, int(dst_member), int(count)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def spectrum_abs(series, dt: float, omegas, stream=None):
+    import torch
+    series = torch.as_tensor(series, dtype=torch.complex128, device="cuda").contiguous()
+    om = torch.as_tensor(omegas, dtype=torch.float64, device=series.device).contiguous()
+    out = torch.empty_like(om)
+    s = stream if stream is not None else torch.cuda.current_stream(series.device)
+    _check(lib().qhfpe_spectrum_abs(_ptr(series), series.numel(), float(dt), _ptr(om), om.numel(), _ptr(out),
+                                    ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
+def spectrum_corr(r3, dt1: float, dt3: float, omega1, omega3, stream=None):
+    """r3: complex [n1][n3] for one waiting time; returns [len(omega3), len(omega1)]."""
+    import torch
+    r3 = torch.as_tensor(r3, dtype=torch.complex128, device="cuda").contiguous()
+    w1 = torch.as_tensor(omega1, dtype=torch.float64, device=r3.device).contiguous()
+    w3 = torch.as_tensor(omega3, dtype=torch.float64, device=r3.device).contiguous()
+    n1, n3 = r3.shape
+    work = torch.empty((n1, w3.numel(), 2), dtype=torch.float64, device=r3.device)
+    out = torch.empty((w3.numel(), w1.numel()), dtype=torch.float64, device=r3.device)
+    s = stream if stream is not None else torch.cuda.current_stream(r3.device)
+    _check(lib().qhfpe_spectrum_corr(_ptr(r3), n1, n3, float(dt1), float(dt3), _ptr(w1), w1.numel(), _ptr(w3),
+                                     w3.numel(), _ptr(work), _ptr(out), ctypes.c_void_p(s.cuda_stream)))
+    return out

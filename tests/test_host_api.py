@@ -1,0 +1,88 @@
+"""CPU tests of the C-ABI library: it loads without a GPU, exports every
+entry point that include/qhfpe.h declares, and validates parameters on the
+host (qhfpe_workspace_bytes touches no GPU)."""
+
+import ctypes
+
+import pytest
+
+from paper_1706_09590_amd import inputs, qhfpe
+
+
+def test_library_exports_every_declared_symbol():
+    L = qhfpe.lib()
+    names = qhfpe.declared_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes_scales_with_batch_and_precision():
+    m = inputs.SMALL_ABSORPTION["model"]
+    b64 = qhfpe.workspace_bytes(m, 1, "fp64")
+    b32 = qhfpe.workspace_bytes(m, 1, "fp32")
+    b64x4 = qhfpe.workspace_bytes(m, 4, "fp64")
+    state = 4 * 4 * 48 * 48
+    assert b64 >= 3 * state * 8
+    assert b32 >= 3 * state * 4 and b32 < b64
+    assert b64x4 >= 4 * 3 * state * 8
+
+
+@pytest.mark.parametrize("override,code", [
+    (dict(np=50), qhfpe.EUNSUPPORTED),
+    (dict(np=512), qhfpe.EUNSUPPORTED),
+    (dict(n_states=1, poly=[[[0, 0, .5, 0, 0]]], mu=[[0]]), qhfpe.EUNSUPPORTED),
+    (dict(nq=3), qhfpe.EINVAL),
+    (dict(depth=-1), qhfpe.EINVAL),
+    (dict(dt=0.0), qhfpe.EINVAL),
+    (dict(q_min=1.0, q_max=1.0), qhfpe.EINVAL),
+    (dict(beta=10.0), qhfpe.EUNSUPPORTED),         # beta hbar gamma >= 2 pi with the correction
+    (dict(poly=[[[0, 0, .5, 0, 0], [0.3, 0.1, 0, 0, 0]], [[0.3, 0.1, 0, 0, 0], [1, 0, .5, 0, 0]]]),
+     qhfpe.EUNSUPPORTED),                            # q-dependent coupling
+    (dict(poly=[[[0, 0, .5, 0, 0], [0.3, 0, 0, 0, 0]], [[0.2, 0, 0, 0, 0], [1, 0, .5, 0, 0]]]),
+     qhfpe.EINVAL),                                  # not symmetric
+    (dict(mu=[[0, 1], [0.5, 0]]), qhfpe.EINVAL),
+])
+def test_parameter_validation(override, code):
+    m = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], **override)
+    with pytest.raises(qhfpe.QHFPEError) as ei:
+        qhfpe.workspace_bytes(m)
+    assert ei.value.code == code
+    assert qhfpe.lib().qhfpe_last_error().decode() != ""
+
+
+def test_batch_and_precision_validation():
+    m = inputs.SMALL_ABSORPTION["model"]
+    p = qhfpe.make_params(m, 0, "fp64")
+    n = ctypes.c_size_t(0)
+    assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.EINVAL
+    p = qhfpe.make_params(m, 1, "fp64")
+    p.precision = 7
+    assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.EINVAL
+    p = qhfpe.make_params(m, 1, "fp64")
+    p.reserved = 1
+    assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.EINVAL
+
+
+def test_null_arguments_rejected_without_gpu():
+    L = qhfpe.lib()
+    n = ctypes.c_size_t(0)
+    assert L.qhfpe_workspace_bytes(None, ctypes.byref(n)) == qhfpe.EINVAL
+    p = qhfpe.make_params(inputs.SMALL_ABSORPTION["model"])
+    assert L.qhfpe_workspace_bytes(ctypes.byref(p), None) == qhfpe.EINVAL
+    h = ctypes.c_void_p()
+    assert L.qhfpe_create(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == qhfpe.EINVAL
+    assert L.qhfpe_step(None, 1, 1, None) == qhfpe.EINVAL
+    assert L.qhfpe_apply_dipole(None, 0) == qhfpe.EINVAL
+    assert L.qhfpe_destroy(None) == qhfpe.OK
+
+
+def test_workload_surfaces_are_the_stated_quartics():
+    import numpy as np
+    poly = np.array(inputs.two_state_surfaces(0.3))
+    q = np.linspace(-6, 8, 11)
+    ug = np.polynomial.polynomial.polyval(q, poly[0, 0])
+    ue = np.polynomial.polynomial.polyval(q, poly[1, 1])
+    np.testing.assert_allclose(ug, 0.5 * q ** 2 + 0.05 * q ** 4, rtol=1e-14, atol=1e-12)
+    np.testing.assert_allclose(ue, 0.5 * (q - 2) ** 2 - 1.5 + 0.05 * (q - 2) ** 4 + 8, rtol=1e-14, atol=1e-12)
+    assert poly[0, 1, 0] == 0.3 and poly[1, 0, 0] == 0.3
