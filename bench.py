@@ -1,0 +1,215 @@
+"""Benchmark of the MS-QHFPE hot path on one MI355X.
+
+One bench step = the whole path for the production-size linear-absorption
+workload: for each bath strength zeta in {0.1, 1.0}: thermal initial state,
+impulsive mu^x, 20000 RK4 steps of the 256 x 256, depth-8 two-state
+hierarchy with Tr{mu W^(0)} sampled every step (FP64 reductions), and the
+absorption spectrum on omega in [0, 20] (2001 points).  Inputs are resident
+in HBM before the timed region; the handles are created beforehand.
+
+Prints one JSON line (metric: hierarchy cell-updates per second).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STAGE_SOURCES = ["paper_1706_09590_amd/csrc/stage_kernel.hpp", "paper_1706_09590_amd/csrc/device_common.hpp"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in STAGE_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(precision: str):
+    """HBM bytes per stage launch from the committed rocprofv3 --pmc summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"stage_kernel_256x256_depth8_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(model: dict, nsteps: int = 4):
+    """The FP64 oracle, single-threaded, on a bounded sample: `nsteps` RK4
+    steps of the same 256 x 256 depth-8 hierarchy (zeta = 1.0)."""
+    for v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
+        os.environ[v] = "1"
+    import numpy as np
+
+    from oracle import qhfpe_oracle as O
+    m = O.Model(n_states=model["n_states"], nq=model["nq"], np_=model["np"], q_min=model["q_min"],
+                q_max=model["q_max"], p_min=model["p_min"], p_max=model["p_max"], depth=model["depth"],
+                zeta=model["zeta"], gamma=model["gamma"], beta=model["beta"], dt=model["dt"],
+                poly=np.array(model["poly"]), mu=np.array(model["mu"]))
+    W = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
+    tables = O.moyal_tables(m)
+    W = O.rk4_step(m, W, tables=tables)  # warm caches
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        W = O.rk4_step(m, W, tables=tables)
+        O.trace_mu(m, W)
+    dt = time.perf_counter() - t0
+    cells = (m.depth + 1) * m.nq * m.np_
+    return dict(value=nsteps * cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{nsteps} RK4 steps (+trace) of the 256x256 depth-8 two-state hierarchy, "
+                       f"zeta=1.0, FP64 NumPy, 1 thread, {dt:.1f} s")
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 10):
+    """Plain device copy of a known size (for scaling the FETCH_SIZE/WRITE_SIZE counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_probe_bytes=nbytes, reps=reps)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--nsteps", type=int, default=20000, help="RK4 steps per propagation")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the propagations of this workload "
+              "shard over independent batch members, and this build measures the single-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_1706_09590_amd import inputs, qhfpe
+
+    work = inputs.PRODUCTION_ABSORPTION
+    base = work["model"]
+    zetas = work["zetas"]
+    nsteps = args.nsteps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    omegas = torch.linspace(0.0, 20.0, 2001, dtype=torch.float64, device=dev)
+
+    def run_leg(precision: str, steps: int, warmup: int):
+        # both bath strengths run as one batch of independent members
+        P = qhfpe.Propagator(base, batch=len(zetas), precision=precision, device=dev, stream=stream)
+        for i, z in enumerate(zetas):
+            P.set_member_bath(i, z, base["gamma"], base["beta"])
+        resp = torch.empty((len(zetas), nsteps + 1), dtype=torch.complex128, device=dev)
+        spec = [None] * len(zetas)
+
+        def one_step():
+            P.init_thermal(1.0)
+            P.apply_dipole()
+            P.step(nsteps, 1, out=resp)
+            for i in range(len(zetas)):
+                spec[i] = qhfpe.spectrum_abs((1j / base["hbar"]) * resp[i], base["dt"], omegas, stream=stream)
+
+        for _ in range(warmup):
+            one_step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_s = e0.elapsed_time(e1) / 1e3
+        cells = (base["depth"] + 1) * base["nq"] * base["np"]
+        updates = steps * len(zetas) * nsteps * cells
+        launches = steps * nsteps * 4
+        w = 8 if precision == "fp64" else 4
+        nc = base["n_states"] ** 2
+        # algorithmic bytes per RK4 step and cell: stage 1 reads y (as v and y) and writes
+        # v_a (2 passes); stages 2-4 read v, read y and write (3 passes each)
+        bytes_per_launch = 11 * nc * w * cells * len(zetas) / 4.0
+        launch_s = gpu_s / launches
+        achieved = bytes_per_launch / launch_s / 1e9
+        traffic = read_traffic(precision)
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
+                    avg_launch_us=round(launch_s * 1e6, 3), bytes_per_launch=bytes_per_launch,
+                    kernel_source_sha=kernel_source_sha())
+        out = dict(value=updates / wall, wall_s=wall, gpu_s=gpu_s, ms_per_step=1e3 * wall / steps,
+                   roofline=roof, resp=resp.cpu().numpy(), spec=[s.cpu().numpy() for s in spec])
+        P.close()
+        return out
+
+    main_leg = run_leg(args.precision, args.steps, args.warmup)
+    line = {
+        "metric": "hierarchy cell-updates/s",
+        "value": main_leg["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "production-size linear absorption: 2-state quartic surfaces, 256x256 (q,p) grid, "
+                        f"depth 8, zeta in {zetas}, beta=1, gamma=1, RK4 dt=0.002, {nsteps} steps, "
+                        "R1 sampled every step, I_abs on 2001 frequencies",
+            "n_states": 2, "nq": 256, "np": 256, "depth": 8, "rk4_steps": nsteps, "zetas": zetas,
+            "precision": args.precision, "parallelism": "single GPU, zetas as one batch of 2 members",
+        },
+        "roofline": main_leg["roofline"],
+        "gpu_event_s": main_leg["gpu_s"],
+    }
+    if not args.no_fp32_leg and args.precision == "fp64":
+        leg = run_leg("fp32", 1, 1)
+        errs = []
+        for s32, s64 in zip(leg["spec"], main_leg["spec"]):
+            errs.append(float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64))))
+        line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
+                                roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(inputs.model_dict(base, zeta=1.0))
+        line["cpu_baseline"] = cb
+    print(json.dumps(line, default=float))
+
+
+if __name__ == "__main__":
+    main()

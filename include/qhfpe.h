@@ -106,10 +106,16 @@ int qhfpe_set_state(qhfpe_t* h, const double* d_canon, int32_t phase, int32_t me
 int qhfpe_get_state(qhfpe_t* h, double* d_canon, int32_t member);
 int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
 
+/* Per-member Drude bath (Sec. II, Eq. (Drude-J)) for parameter sweeps in one
+ * batch: member -1 sets all members.  At create every member takes the
+ * params' zeta, gamma, beta; the low_temp_correction flag of the params
+ * applies.  Synchronous. */
+int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta);
+
 /* Initial state (Sec. III protocol; harmonic thermal Wigner function):
  * W^(0)_00(p, q) = tanh(b)/(pi hbar) exp(-tanh(b) [p^2/(m hbar omega) + m omega q^2/hbar]),
- * b = beta hbar omega/2, plus d_noise[i][a] (FP64 [nq][np], may be NULL);
- * every other entry 0, phase 0, all members. */
+ * b = beta hbar omega/2 with each member's beta, plus d_noise[i][a] (FP64
+ * [nq][np], may be NULL); every other entry 0, phase 0, all members. */
 int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise);
 
 /* Impulsive excitation mu^x W = mu W - W mu on every level and member

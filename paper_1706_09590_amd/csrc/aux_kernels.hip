@@ -152,7 +152,8 @@ __global__ void __launch_bounds__(kBlock) dipole_kernel(GridDesc g, T* __restric
 template <typename T, int NS>
 __global__ void __launch_bounds__(kBlock)
     thermal_kernel(GridDesc g, T* __restrict__ packed, double q0, double dq, double p0, double dp,
-                   double tanh_b, double omega, double mass, double hbar, const double* __restrict__ noise) {
+                   const double* __restrict__ bath, double omega, double mass, double hbar,
+                   const double* __restrict__ noise) {
   constexpr int NC = NS * NS;
   const long long gridn = (long long)g.nq * g.np;
   const long long cells = (long long)g.levels * gridn;
@@ -164,6 +165,8 @@ __global__ void __launch_bounds__(kBlock)
   T* p = packed + (long long)b * g.member_stride + (long long)n * g.level_stride + ia;
   double w = 0.0;
   if (n == 0) {
+    // b = beta hbar omega / 2 with this member's beta
+    const double tanh_b = tanh(0.5 * bath[kBathStride * b + 4] * hbar * omega);
     const int i = (int)(ia / g.np), a = (int)(ia % g.np);
     const double q = q0 + i * dq, pp = p0 + a * dp;
     w = (tanh_b / (M_PI * hbar)) *
@@ -343,11 +346,11 @@ hipError_t launch_dipole(const GridDesc& g, void* packed, const double mu[3][3],
 }
 
 hipError_t launch_thermal(const GridDesc& g, void* packed, double q0, double dq, double p0, double dp,
-                          double tanh_b, double omega, double mass, double hbar, const double* noise,
+                          const double* bath, double omega, double mass, double hbar, const double* noise,
                           hipStream_t s) {
   const dim3 grid = cell_grid(g, g.batch);
 #define F(T, NS) hipLaunchKernelGGL((thermal_kernel<T, NS>), grid, dim3(kBlock), 0, s, g, static_cast<T*>(packed), \
-                                    q0, dq, p0, dp, tanh_b, omega, mass, hbar, noise)
+                                    q0, dq, p0, dp, bath, omega, mass, hbar, noise)
   QHFPE_DISPATCH(g, F);
 #undef F
   return hipGetLastError();

@@ -63,6 +63,12 @@ __device__ __forceinline__ cx<T> rot48(cx<T> x) {
     return {-x.re, -x.im};
   } else if constexpr (e == 36) {
     return {x.im, -x.re};
+  } else if constexpr (e % 6 == 0) {
+    // odd multiples of an eighth turn: (+-1 +- i)/sqrt(2)
+    const T h = T(0.70710678118654752440);
+    constexpr int cs = (e == 6 || e == 42) ? 1 : -1;
+    constexpr int sn = (e == 6 || e == 18) ? 1 : -1;
+    return {h * (T(cs) * x.re - T(sn) * x.im), h * (T(sn) * x.re + T(cs) * x.im)};
   } else {
     const T c = T(kCos48[e]);
     const T s = T(kSin48[e]);

@@ -44,6 +44,8 @@ struct Layout {
   long long member_elems = 0, level_elems = 0, comp_elems = 0;
   size_t state_bytes = 0;
   size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
+  size_t off_dtab = 0, off_gtab = 0, off_bath = 0;
+  int n1 = 0, n2 = 0;
   size_t total = 0;
   size_t red_count = 0;
   int tq = 0, ntiles = 0;
@@ -94,8 +96,8 @@ Layout make_layout(const qhfpe_params* p) {
   L.level_elems = L.comp_elems * nc;
   L.member_elems = L.level_elems * (p->depth + 1);
   L.state_bytes = align_up((size_t)L.member_elems * p->batch * L.elem);
-  L.tq = pl->tq;
-  L.ntiles = (p->nq + pl->tq - 1) / pl->tq;
+  L.tq = plan_tq(p->np, (int)L.elem, p->n_states);
+  L.ntiles = (p->nq + L.tq - 1) / L.tq;
   const long long cells = (long long)(p->depth + 1) * p->nq * p->np;
   const long long pack_blocks = (cells + kBlock - 1) / kBlock;
   L.red_count = (size_t)p->batch * (size_t)std::max<long long>(2 * pack_blocks, 1024);
@@ -110,12 +112,90 @@ Layout make_layout(const qhfpe_params* p) {
   off += align_up((size_t)p->batch * kRespSlots * L.ntiles * sizeof(double));
   L.off_red = off;
   off += align_up(L.red_count * sizeof(double));
+  L.n1 = pl->n1;
+  L.n2 = pl->n2;
   L.off_tw = off;
-  off += align_up((size_t)p->np * 2 * L.elem);
+  off += align_up((size_t)pl->n1 * (pl->n2 + 1) * 2 * L.elem);
+  const int ns = p->n_states;
+  L.off_dtab = off;
+  off += align_up((size_t)ns * L.comp_elems * L.elem);
+  L.off_gtab = off;
+  off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
+  L.off_bath = off;
+  off += align_up((size_t)p->batch * kBathStride * sizeof(double));
   L.off_flag = off;
   off += kAlign;
   L.total = off;
   return L;
+}
+
+// r0/m, gamma, c0, c_delta of the Drude bath (single exponential plus the
+// delta-correlated term that absorbs the Matsubara frequencies).
+void bath_constants(const qhfpe_params& p, double zeta, double gamma, double beta, double out[kBathStride]) {
+  for (int k = 0; k < kBathStride; ++k) out[k] = 0.0;
+  out[0] = zeta;  // r0 / m with r0 = m zeta
+  out[1] = gamma;
+  out[4] = beta;
+  if (p.low_temp_correction) {
+    const double x = 0.5 * beta * p.hbar * gamma;
+    out[2] = 0.5 * p.mass * zeta * p.hbar * gamma * std::cos(x) / std::sin(x);
+    out[3] = p.mass * zeta / beta - out[2];
+  } else {
+    out[2] = p.mass * zeta / beta;
+    out[3] = 0.0;
+  }
+}
+
+double poly_value(const double* c, double x) {
+  return (((c[4] * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0];
+}
+
+// r-space multipliers of the potential term at (q_i, r_m), with the argument
+// q +- r/2 clamped to the q-grid and the Nyquist column averaged over +-r.
+void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<double>& dtab,
+                       std::vector<double>& gtab) {
+  const int ns = p.n_states, nq = p.nq, np = p.np;
+  const double dr = 2.0 * M_PI * p.hbar / (np * dp);
+  const double qlo = p.q_min, qhi = p.q_min + (nq - 1) * dq;
+  auto clampq = [&](double x) { return x < qlo ? qlo : (x > qhi ? qhi : x); };
+  const size_t plane = (size_t)nq * np;
+  dtab.assign((size_t)ns * plane, 0.0);
+  gtab.assign((size_t)(ns * (ns - 1) / 2) * plane, 0.0);
+  for (int i = 0; i < nq; ++i) {
+    const double q = p.q_min + i * dq;
+    for (int m = 0; m < np; ++m) {
+      const int mh = (m <= np / 2) ? m : m - np;
+      const double xp = clampq(q + 0.5 * mh * dr), xm = clampq(q - 0.5 * mh * dr);
+      const bool nyq = (m == np / 2);
+      double up[QHFPE_MAX_STATES], um[QHFPE_MAX_STATES];
+      for (int j = 0; j < ns; ++j) {
+        up[j] = poly_value(p.poly[j][j], xp);
+        um[j] = poly_value(p.poly[j][j], xm);
+        if (nyq) up[j] = um[j] = 0.5 * (up[j] + um[j]);
+        dtab[j * plane + (size_t)i * np + m] = (up[j] - um[j]) / (2.0 * p.hbar * np);
+      }
+      int pr = 0;
+      for (int j = 0; j < ns; ++j)
+        for (int k = j + 1; k < ns; ++k, ++pr)
+          gtab[pr * plane + (size_t)i * np + m] = (up[j] - um[k]) / (p.hbar * np);
+    }
+  }
+}
+
+// n1 x (n2 + 1) padded table of exp(+2 pi i (n2 k1 mod np) / np)
+void twiddle_table(int np, int n1, int n2, std::vector<double>& tw) {
+  tw.assign((size_t)n1 * (n2 + 1) * 2, 0.0);
+  for (int k1 = 0; k1 < n1; ++k1)
+    for (int j = 0; j < n2; ++j) {
+      const double ang = 2.0 * M_PI * (double)((j * k1) % np) / (double)np;
+      tw[2 * ((size_t)k1 * (n2 + 1) + j)] = std::cos(ang);
+      tw[2 * ((size_t)k1 * (n2 + 1) + j) + 1] = std::sin(ang);
+    }
+}
+
+template <typename T>
+std::vector<T> convert(const std::vector<double>& x) {
+  return std::vector<T>(x.begin(), x.end());
 }
 
 }  // namespace
@@ -127,7 +207,7 @@ struct qhfpe_handle {
   hipStream_t stream = nullptr;
   int phase = 0;
   int ns = 0, nc = 0, levels = 0;
-  double r0 = 0, c0 = 0, cdelta = 0, dq = 0, dp = 0, dr = 0;
+  double dq = 0, dp = 0;
 
   void* y() const { return ws + L.off_y; }
   void* va() const { return ws + L.off_va; }
@@ -135,6 +215,9 @@ struct qhfpe_handle {
   double* partials() const { return reinterpret_cast<double*>(ws + L.off_partials); }
   double* red() const { return reinterpret_cast<double*>(ws + L.off_red); }
   void* twiddle() const { return ws + L.off_tw; }
+  void* dtab() const { return ws + L.off_dtab; }
+  void* gtab() const { return ws + L.off_gtab; }
+  double* bath() const { return reinterpret_cast<double*>(ws + L.off_bath); }
   int* flag() const { return reinterpret_cast<int*>(ws + L.off_flag); }
 
   GridDesc grid() const {
@@ -158,40 +241,34 @@ struct qhfpe_handle {
     a.y = yb;
     a.out = out;
     a.partials = nullptr;
-    a.twiddle = twiddle();
+    a.twiddle2 = twiddle();
+    a.dtab = dtab();
+    a.gtab = gtab();
+    a.bath = bath();
     a.slot = 0;
     a.nq = p.nq;
     a.depth = p.depth;
     a.ntiles = L.ntiles;
+    a.batch = p.batch;
+    a.nblocks_padded = (L.ntiles * levels * p.batch + 7) / 8 * 8;
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;
     a.coef = coef;
     a.dq = dq;
     a.dp = dp;
-    a.dr = dr;
-    a.q0 = p.q_min;
     a.p0 = p.p_min;
-    a.qlo = p.q_min;
-    a.qhi = p.q_min + (p.nq - 1) * dq;
     a.inv_mass = 1.0 / p.mass;
-    a.inv_hbar = 1.0 / p.hbar;
-    a.zeta = r0 / p.mass;
-    a.gamma = p.gamma;
-    a.c0 = c0;
-    a.cdelta = cdelta;
-    for (int j = 0; j < ns; ++j) {
-      for (int k = 0; k < 5; ++k) a.poly[j][k] = p.poly[j][j][k];
+    for (int j = 0; j < ns; ++j)
       for (int l = 0; l < ns; ++l) {
         a.coup[j][l] = (j == l) ? 0.0 : p.poly[j][l][0] / p.hbar;
         a.mu[j][l] = p.mu[j][l];
       }
-    }
     return a;
   }
 
   hipError_t launch(const StageArgs& a) const {
-    const int nblocks = L.ntiles * levels * p.batch;
+    const int nblocks = a.nblocks_padded;
     if (p.precision == QHFPE_FP64)
       return ns == 2 ? launch_stage_f64_ns2(p.np, a, nblocks, stream) : launch_stage_f64_ns3(p.np, a, nblocks, stream);
     return ns == 2 ? launch_stage_f32_ns2(p.np, a, nblocks, stream) : launch_stage_f32_ns3(p.np, a, nblocks, stream);
@@ -273,29 +350,31 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->levels = params->depth + 1;
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
-  h->dr = 2.0 * M_PI * params->hbar / (params->np * h->dp);
-  h->r0 = params->mass * params->zeta;
-  if (params->low_temp_correction) {
-    const double x = 0.5 * params->beta * params->hbar * params->gamma;
-    h->c0 = 0.5 * params->mass * params->zeta * params->hbar * params->gamma * std::cos(x) / std::sin(x);
-    h->cdelta = params->mass * params->zeta / params->beta - h->c0;
-  } else {
-    h->c0 = params->mass * params->zeta / params->beta;
-    h->cdelta = 0.0;
-  }
-  // twiddles exp(+2 pi i j / np), computed in FP64 and rounded once
-  const int np = params->np;
-  std::vector<double> tw64(2 * (size_t)np);
-  std::vector<float> tw32(2 * (size_t)np);
-  for (int j = 0; j < np; ++j) {
-    const double ang = 2.0 * M_PI * (double)j / (double)np;
-    tw64[2 * j] = std::cos(ang);
-    tw64[2 * j + 1] = std::sin(ang);
-    tw32[2 * j] = (float)tw64[2 * j];
-    tw32[2 * j + 1] = (float)tw64[2 * j + 1];
-  }
-  const void* src = (params->precision == QHFPE_FP64) ? (const void*)tw64.data() : (const void*)tw32.data();
-  hipError_t e = hipMemcpyAsync(h->twiddle(), src, (size_t)np * 2 * L.elem, hipMemcpyHostToDevice, h->stream);
+  // setup tables, computed in FP64 and rounded once to the state precision
+  std::vector<double> tw, dt, gt;
+  twiddle_table(params->np, L.n1, L.n2, tw);
+  multiplier_tables(*params, h->dq, h->dp, dt, gt);
+  std::vector<double> bath((size_t)params->batch * kBathStride);
+  double bc[kBathStride];
+  bath_constants(*params, params->zeta, params->gamma, params->beta, bc);
+  for (int b = 0; b < params->batch; ++b)
+    for (int k = 0; k < kBathStride; ++k) bath[kBathStride * b + k] = bc[k];
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const std::vector<double>& src) {
+    if (e != hipSuccess || src.empty()) return;
+    if (params->precision == QHFPE_FP64) {
+      e = hipMemcpyAsync(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    } else {
+      std::vector<float> f = convert<float>(src);
+      e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // f is a temporary
+    }
+  };
+  up(h->twiddle(), tw);
+  up(h->dtab(), dt);
+  up(h->gtab(), gt);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->bath(), bath.data(), bath.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->y(), 0, 3 * L.state_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->flag(), 0, sizeof(int), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -310,6 +389,27 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
 int qhfpe_destroy(qhfpe_t* h) {
   if (!h) return QHFPE_OK;
   delete h;
+  return QHFPE_OK;
+}
+
+int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta) {
+  if (int rc = check_handle(h)) return rc;
+  if (member < -1 || member >= h->p.batch) return fail(QHFPE_EINVAL, "member out of range");
+  if (!(zeta >= 0) || !(gamma > 0) || !(beta > 0) || !std::isfinite(zeta) || !std::isfinite(gamma) ||
+      !std::isfinite(beta))
+    return fail(QHFPE_EINVAL, "need finite zeta >= 0, gamma > 0, beta > 0");
+  if (h->p.low_temp_correction && !(beta * h->p.hbar * gamma < 2.0 * M_PI))
+    return fail(QHFPE_EUNSUPPORTED, "low-temperature correction needs beta hbar gamma < 2 pi");
+  double bc[kBathStride];
+  bath_constants(h->p, zeta, gamma, beta, bc);
+  const int first = member < 0 ? 0 : member;
+  const int count = member < 0 ? h->p.batch : 1;
+  std::vector<double> buf((size_t)count * kBathStride);
+  for (int b = 0; b < count; ++b)
+    for (int k = 0; k < kBathStride; ++k) buf[kBathStride * b + k] = bc[k];
+  HIP_TRY(hipMemcpyAsync(h->bath() + kBathStride * first, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return QHFPE_OK;
 }
 
@@ -365,8 +465,7 @@ int qhfpe_get_state(qhfpe_t* h, double* d_canon, int32_t member) {
 int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise) {
   if (int rc = check_handle(h)) return rc;
   if (!(omega > 0) || !std::isfinite(omega)) return fail(QHFPE_EINVAL, "omega must be finite and > 0");
-  const double tb = std::tanh(0.5 * h->p.beta * h->p.hbar * omega);
-  HIP_TRY(launch_thermal(h->grid(), h->y(), h->p.q_min, h->dq, h->p.p_min, h->dp, tb, omega, h->p.mass,
+  HIP_TRY(launch_thermal(h->grid(), h->y(), h->p.q_min, h->dq, h->p.p_min, h->dp, h->bath(), omega, h->p.mass,
                          h->p.hbar, d_noise, h->stream));
   h->phase = 0;
   return QHFPE_OK;

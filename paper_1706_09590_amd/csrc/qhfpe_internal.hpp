@@ -13,16 +13,15 @@ namespace qhfpe {
 
 constexpr int kBlock = 256;        // threads per workgroup of every grid kernel
 constexpr int kRespSlots = 256;    // response samples buffered between finalisations
+constexpr int kBathStride = 8;     // doubles per member in the bath table
 
-// Two-pass FFT plan along p (np = n1 * n2, n1 even) and the q-tile width of
-// one stage workgroup, for every supported np.
+// Two-pass FFT plan along p (np = n1 * n2, n1 even) for every supported np.
 struct Plan {
-  int np, n1, n2, tq;
+  int np, n1, n2;
 };
 constexpr Plan kPlans[] = {
-    {8, 4, 2, 16},    {12, 4, 3, 16},  {16, 4, 4, 16},   {24, 6, 4, 16},
-    {32, 8, 4, 16},   {48, 8, 6, 16},  {64, 8, 8, 16},   {96, 12, 8, 8},
-    {128, 16, 8, 8},  {192, 16, 12, 4}, {256, 16, 16, 4},
+    {8, 4, 2},   {12, 4, 3},  {16, 4, 4},   {24, 6, 4},    {32, 8, 4},    {48, 8, 6},
+    {64, 8, 8},  {96, 12, 8}, {128, 16, 8}, {192, 16, 12}, {256, 16, 16},
 };
 inline const Plan* find_plan(int np) {
   for (const Plan& p : kPlans)
@@ -30,25 +29,35 @@ inline const Plan* find_plan(int np) {
   return nullptr;
 }
 
+// Stage workgroup shape: G = max(1, 256/np) groups of np threads; each
+// thread owns one p node of CPT consecutive q columns; a tile is TQ = G*CPT
+// columns (even, so three-state tiles can pair columns).
+constexpr int plan_groups(int np) { return np >= 256 ? 1 : 256 / np; }
+constexpr int plan_cpt(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
+constexpr int plan_tq(int np, int elem_bytes, int ns) { return plan_groups(np) * plan_cpt(elem_bytes, ns); }
+
 // Arguments of the fused RK-stage kernel (passed by value).
 struct StageArgs {
-  const void* v;        // stage input, packed [B][N+1][nc][nq][np]
-  const void* y;        // RK4 base state (nullptr: treated as zero)
-  void* out;            // y + coef * L v
-  double* partials;     // [B][kRespSlots][ntiles] level-0 trace partials, or nullptr
-  const void* twiddle;  // np complex entries exp(+2 pi i j/np) in the state precision
+  const void* v;         // stage input, packed [B][N+1][nc][nq][np]
+  const void* y;         // RK4 base state (nullptr: treated as zero)
+  void* out;             // y + coef * L v
+  double* partials;      // [B][kRespSlots][ntiles] level-0 trace partials, or nullptr
+  const void* twiddle2;  // [n1][n2+1] complex exp(+2 pi i (n2 k1 mod np)/np), state precision
+  const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
+  const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
+  const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   int slot;
   int nq;
   int depth;
   int ntiles;
+  int batch;
+  int nblocks_padded;       // grid size: ntiles * (depth+1) * batch rounded up to a multiple of 8
   long long member_stride;  // elements per member
   long long level_stride;   // elements per level
   long long comp_stride;    // elements per packed component (nq * np)
   double coef;
-  double dq, dp, dr, q0, p0, qlo, qhi;
-  double inv_mass, inv_hbar;
-  double zeta, gamma, c0, cdelta;
-  double poly[QHFPE_MAX_STATES][5];                    // diagonal surfaces
+  double dq, dp, p0;
+  double inv_mass;
   double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];     // off-diagonal couplings / hbar
   double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
 };
@@ -76,7 +85,7 @@ hipError_t launch_unpack(const GridDesc& g, const void* packed, int phase, doubl
                          int member_offset, int nmembers, hipStream_t s);
 hipError_t launch_dipole(const GridDesc& g, void* packed, const double mu[3][3], hipStream_t s);
 hipError_t launch_thermal(const GridDesc& g, void* packed, double q0, double dq, double p0,
-                          double dp, double tanh_b, double omega, double mass, double hbar,
+                          double dp, const double* bath, double omega, double mass, double hbar,
                           const double* noise, hipStream_t s);
 hipError_t launch_trace_partials(const GridDesc& g, const void* packed, const double mu[3][3],
                                  int tq, int ntiles, double* partials, int slot, hipStream_t s);

@@ -27,194 +27,215 @@
 
 namespace qhfpe {
 
+// FFT split np = N1 * N2 per supported np.
 template <int NP>
-struct PlanOf;
-#define QHFPE_PLAN(NP_, N1_, N2_, TQ_)                 \
-  template <>                                          \
-  struct PlanOf<NP_> {                                 \
-    static constexpr int N1 = N1_, N2 = N2_, TQ = TQ_; \
+struct FftSplit;
+#define QHFPE_SPLIT(NP_, N1_, N2_) \
+  template <>                      \
+  struct FftSplit<NP_> {           \
+    static constexpr int N1 = N1_, N2 = N2_; \
   };
-QHFPE_PLAN(8, 4, 2, 16)
-QHFPE_PLAN(12, 4, 3, 16)
-QHFPE_PLAN(16, 4, 4, 16)
-QHFPE_PLAN(24, 6, 4, 16)
-QHFPE_PLAN(32, 8, 4, 16)
-QHFPE_PLAN(48, 8, 6, 16)
-QHFPE_PLAN(64, 8, 8, 16)
-QHFPE_PLAN(96, 12, 8, 8)
-QHFPE_PLAN(128, 16, 8, 8)
-QHFPE_PLAN(192, 16, 12, 4)
-QHFPE_PLAN(256, 16, 16, 4)
-#undef QHFPE_PLAN
+QHFPE_SPLIT(8, 4, 2)
+QHFPE_SPLIT(12, 4, 3)
+QHFPE_SPLIT(16, 4, 4)
+QHFPE_SPLIT(24, 6, 4)
+QHFPE_SPLIT(32, 8, 4)
+QHFPE_SPLIT(48, 8, 6)
+QHFPE_SPLIT(64, 8, 8)
+QHFPE_SPLIT(96, 12, 8)
+QHFPE_SPLIT(128, 16, 8)
+QHFPE_SPLIT(192, 16, 12)
+QHFPE_SPLIT(256, 16, 16)
+#undef QHFPE_SPLIT
+
+// Launch shape of the stage kernel (see plan_tq): NT = np * G threads.
+template <typename T, int NS, int NP>
+struct PlanOf {
+  static constexpr int N1 = FftSplit<NP>::N1, N2 = FftSplit<NP>::N2;
+  static constexpr int G = plan_groups(NP);
+  static constexpr int NT = NP * G;
+  static constexpr int CPT = plan_cpt((int)sizeof(T), NS);
+  static constexpr int TQ = G * CPT;
+};
 
 // Upwind coefficients (x60) for p >= 0 on offsets -3..2; the p < 0 stencil
 // is the mirror image with opposite sign (Sec. III).
 __device__ constexpr double kUpwind[6] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0};
 
-template <typename T, int NS>
-__device__ __forceinline__ T poly_eval(const double (&c)[QHFPE_MAX_STATES][5], int j, T x) {
-  T r = T(c[j][4]);
-  r = r * x + T(c[j][3]);
-  r = r * x + T(c[j][2]);
-  r = r * x + T(c[j][1]);
-  r = r * x + T(c[j][0]);
-  return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T clampT(T x, T lo, T hi) {
-  return x < lo ? lo : (x > hi ? hi : x);
+// Fixed-slot block order: a tile's q neighbours and its hierarchy
+// neighbours are placed on the same XCD (blocks are dealt round-robin over
+// the 8 XCDs), so halo and level reads hit that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = (nblocks + kXcd - 1) / kXcd;
+  return (bid % kXcd) * per + bid / kXcd;
 }
 
 template <typename T, int NS, int NP>
-__global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
-  using P = PlanOf<NP>;
-  constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ;
+__global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArgs a) {
+  using P = PlanOf<T, NS, NP>;
+  constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ, NT = P::NT, CPT = P::CPT;
   constexpr int NC = NS * NS;
   constexpr int NPAIR = NS * (NS - 1) / 2;
   // complex transforms per tile: diagonal pairs (0,1) per column, (2 of c,
   // 2 of c+1) per column pair when NS = 3, and each off-diagonal pair.
   constexpr int NFFT = TQ + (NS == 3 ? TQ / 2 : 0) + NPAIR * TQ;
-  constexpr int CELLS = TQ * NP;
-  constexpr int CPT = (CELLS + kBlock - 1) / kBlock;
   static_assert(NS == 2 || TQ % 2 == 0, "three-state tiles pair columns");
 
-  __shared__ T sv[TQ * NC * NP];
-  __shared__ cx<T> stw[NP];
+  // LDS columns are padded by one element per N2 block (index a + a / N2),
+  // so the FFT passes that walk a column with stride N2 are free of bank
+  // conflicts.
+  constexpr int LDP = NP + NP / N2;
+  __shared__ T sv[TQ * NC * LDP];   // v^(n) tile, then the potential term in place
+  __shared__ T sg[TQ * NC * LDP];   // field differentiated once along p, then y + coef * local terms
+  __shared__ cx<T> stw[N1 * (N2 + 1)];  // w^(n2 k1), row k1 padded to N2 + 1
 
+  const int nblocks = a.ntiles * (a.depth + 1) * a.batch;
+  const int lb = xcd_logical_block(blockIdx.x, a.nblocks_padded);
+  if (lb >= nblocks) return;
   const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
-  const int tile = bid % a.ntiles;
-  const int rest = bid / a.ntiles;
+  const int tile = lb % a.ntiles;
+  const int rest = lb / a.ntiles;
   const int L = a.depth + 1;
   const int n = rest % L;
   const int b = rest / L;
   const int q0 = tile * TQ;
   const int nq = a.nq;
+  const int ia = tid % NP;           // this thread's p node
+  const int iap = ia + ia / N2;      // its padded LDS index
+  const int cb = (tid / NP) * CPT;   // first of its CPT tile columns
+  const long long cs = a.comp_stride;
 
   const T* __restrict__ v = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
   const T* __restrict__ vn = v + (long long)n * a.level_stride;
-  const long long cs = a.comp_stride;
+  const bool has_up = n < a.depth, has_dn = n >= 1;
+  const T* __restrict__ vu = v + (long long)(has_up ? n + 1 : n) * a.level_stride;
+  const T* __restrict__ vd = v + (long long)(has_dn ? n - 1 : n) * a.level_stride;
+  const T* yp = a.y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride + (long long)n * a.level_stride
+                    : nullptr;
 
-  // ---- P0: twiddles and the v^(n) tile into LDS -------------------------
-  for (int j = tid; j < NP; j += kBlock) stw[j] = static_cast<const cx<T>*>(a.twiddle)[j];
-  for (int e = tid; e < TQ * NC * NP; e += kBlock) {
-    const int c = e / (NC * NP);
-    const int comp = (e / NP) % NC;
-    const int ia = e % NP;
-    const int q = q0 + c;
-    sv[e] = (q < nq) ? vn[comp * cs + (long long)q * NP + ia] : T(0);
-  }
-  __syncthreads();
+  for (int j = tid; j < N1 * (N2 + 1); j += NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
 
-  // ---- P1: local terms into registers -----------------------------------
-  const T dqinv = T(1.0 / (60.0 * a.dq));
-  const T dpinv = T(1.0 / (12.0 * a.dp));
-  const T dp2inv = T(1.0 / (12.0 * a.dp * a.dp));
-  const T dpdpinv = T(1.0 / (144.0 * a.dp * a.dp));
-  const T zeta = T(a.zeta), c0 = T(a.c0), cdel = T(a.cdelta);
-  const T ng = T(n * a.gamma);
-  const T inv_mass = T(a.inv_mass);
-  T coup[NS][NS];
+  const T p = T(a.p0 + ia * a.dp);
+  const double* bath = a.bath + kBathStride * b;
+  const T zeta = T(bath[0]), c0 = T(bath[2]), cdel = T(bath[3]);
+  const T ng = T(n * bath[1]);
+  // kinetic term -(p/m) D_q with the upwind stencil chosen by the sign of p:
+  // coefficients on q offsets -3..3 (one end is zero for either sign)
+  T kc[7];
+  {
+    const T scale = -(p * T(a.inv_mass)) * T(1.0 / (60.0 * a.dq));
+    const bool pos = p >= T(0);
 #pragma unroll
-  for (int j = 0; j < NS; ++j)
-#pragma unroll
-    for (int k = 0; k < NS; ++k) coup[j][k] = T(a.coup[j][k]);
-
-  T acc[CPT][NC];
-#pragma unroll
-  for (int t = 0; t < CPT; ++t) {
-    const int e = tid + t * kBlock;
-#pragma unroll
-    for (int comp = 0; comp < NC; ++comp) acc[t][comp] = T(0);
-    if (e >= CELLS) continue;
-    const int c = e / NP;
-    const int ia = e % NP;
-    const int q = q0 + c;
-    if (q >= nq) continue;
-    const T p = T(a.p0 + ia * a.dp);
-    const int sgn = (p >= T(0)) ? 1 : -1;
-    const int am1 = (ia + NP - 1) % NP, am2 = (ia + NP - 2) % NP;
-    const int ap1 = (ia + 1) % NP, ap2 = (ia + 2) % NP;
-    const T* svc = sv + c * NC * NP;
-    T hv[NC];
-#pragma unroll
-    for (int comp = 0; comp < NC; ++comp) {
-      const T* s = svc + comp * NP;
-      const T w0 = s[ia];
-      hv[comp] = w0;
-      // kinetic: -(p/m) sgn sum_d c_d v(q + sgn d)
-      T dq_acc = T(0);
-#pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        const int off = sgn * (d - 3);
-        const int cc = c + off;
-        const int qq = q + off;
-        T val;
-        if (cc >= 0 && cc < TQ) {
-          val = sv[(cc * NC + comp) * NP + ia];
-        } else {
-          val = (qq >= 0 && qq < nq) ? vn[comp * cs + (long long)qq * NP + ia] : T(0);
-        }
-        dq_acc += T(kUpwind[d]) * val;
-      }
-      T f = -(p * inv_mass) * T(sgn) * dqinv * dq_acc;
-      // damping and the delta-correlated (low-temperature) correction
-      f += -ng * w0;
-      f += cdel * dp2inv * (-s[ap2] + T(16) * s[ap1] - T(30) * w0 + T(16) * s[am1] - s[am2]);
-      // level couplings
-      const long long col = comp * cs + (long long)q * NP;
-      if (n < a.depth) {
-        const T* u = v + (long long)(n + 1) * a.level_stride + col;
-        T g2p = u[ap2], g1p = u[ap1], g1m = u[am1], g2m = u[am2];
-        if (n >= 1) {
-          const T* l = v + (long long)(n - 1) * a.level_stride + col;
-          const T k = ng * c0;
-          g2p += k * l[ap2];
-          g1p += k * l[ap1];
-          g1m += k * l[am1];
-          g2m += k * l[am2];
-          f += ng * zeta * p * l[ia];
-        }
-        f += dpinv * (-g2p + T(8) * g1p - T(8) * g1m + g2m);
-      } else {
-        // terminator: D_p(zeta p v + N gamma c0 v^(N-1)) + c0 D_p D_p v + N gamma zeta p v^(N-1)
-        const T pp2 = T(a.p0 + ap2 * a.dp), pp1 = T(a.p0 + ap1 * a.dp);
-        const T pm1 = T(a.p0 + am1 * a.dp), pm2 = T(a.p0 + am2 * a.dp);
-        T g2p = zeta * pp2 * s[ap2], g1p = zeta * pp1 * s[ap1];
-        T g1m = zeta * pm1 * s[am1], g2m = zeta * pm2 * s[am2];
-        if (n >= 1) {
-          const T* l = v + (long long)(n - 1) * a.level_stride + col;
-          const T k = ng * c0;
-          g2p += k * l[ap2];
-          g1p += k * l[ap1];
-          g1m += k * l[am1];
-          g2m += k * l[am2];
-          f += ng * zeta * p * l[ia];
-        }
-        f += dpinv * (-g2p + T(8) * g1p - T(8) * g1m + g2m);
-        const int ap3 = (ia + 3) % NP, ap4 = (ia + 4) % NP;
-        const int am3 = (ia + NP - 3) % NP, am4 = (ia + NP - 4) % NP;
-        f += c0 * dpdpinv *
-             (s[am4] - T(16) * s[am3] + T(64) * s[am2] + T(16) * s[am1] - T(130) * w0 +
-              T(16) * s[ap1] + T(64) * s[ap2] - T(16) * s[ap3] + s[ap4]);
-      }
-      acc[t][comp] = f;
+    for (int o = -3; o <= 3; ++o) {
+      const double cp = (o <= 2) ? kUpwind[o + 3] : 0.0;
+      const double cn = (o >= -2) ? -kUpwind[3 - o] : 0.0;
+      kc[o + 3] = scale * T(pos ? cp : cn);
     }
-    // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p
-    T cm[NC];
-    commutator_mi<NS, T>(coup, hv, cm);
+  }
+
+  // ---- P1: all global loads of this thread, then local terms -------------
+  T acc[CPT][NC];
+  T yv[CPT][NC];
+  int qc[CPT + 6];
+  bool qin[CPT + 6];
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) acc[t][comp] += cm[comp];
+  for (int j = 0; j < CPT + 6; ++j) {
+    const int q = q0 + cb + j - 3;
+    qin[j] = (q >= 0) && (q < nq);
+    qc[j] = q < 0 ? 0 : (q >= nq ? nq - 1 : q);
+  }
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    const long long co = comp * cs + ia;
+    T w[CPT + 6];
+#pragma unroll
+    for (int j = 0; j < CPT + 6; ++j) w[j] = vn[co + (long long)qc[j] * NP];
+#pragma unroll
+    for (int j = 0; j < CPT + 6; ++j) w[j] = qin[j] ? w[j] : T(0);
+    T up[CPT], dn[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      up[i] = vu[co + (long long)qc[i + 3] * NP];
+      dn[i] = vd[co + (long long)qc[i + 3] * NP];
+      yv[i][comp] = yp ? yp[co + (long long)qc[i + 3] * NP] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      T f = T(0);
+#pragma unroll
+      for (int o = 0; o < 7; ++o) f += kc[o] * w[i + o];
+      const T w0 = w[i + 3];
+      f -= ng * w0;
+      // field differentiated once along p:
+      //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
+      T g = has_up ? up[i] : zeta * p * w0;
+      if (has_dn) {
+        g += ng * c0 * dn[i];
+        f += ng * zeta * p * dn[i];
+      }
+      acc[i][comp] = f;
+      sv[((cb + i) * NC + comp) * LDP + iap] = w0;
+      sg[((cb + i) * NC + comp) * LDP + iap] = qin[i + 3] ? g : T(0);
+    }
   }
   __syncthreads();
 
-  // ---- P2..P5: potential term, in place in LDS ---------------------------
-  // Transform f reads its real part from array re_of(f) and its imaginary
-  // part from im_of(f) (each one p-column of one packed component).
-  auto fft_desc = [&](int f, int& colA, int& compA, int& colB, int& compB, int& kind, int& sj,
-                       int& sk) {
-    // kind 0: two real diagonal components (states sj of colA, sk of colB)
+  // ---- P2: p-stencils and the pointwise coupling commutator ---------------
+  {
+    const T dpinv = T(1.0 / (12.0 * a.dp));
+    const T dp2inv = T(1.0 / (12.0 * a.dp * a.dp));
+    const T dpdpinv = T(1.0 / (144.0 * a.dp * a.dp));
+    auto pd = [](int x) { return x + x / N2; };
+    const int am1 = pd((ia + NP - 1) % NP), am2 = pd((ia + NP - 2) % NP);
+    const int ap1 = pd((ia + 1) % NP), ap2 = pd((ia + 2) % NP);
+    const int am3 = pd((ia + NP - 3) % NP), am4 = pd((ia + NP - 4) % NP);
+    const int ap3 = pd((ia + 3) % NP), ap4 = pd((ia + 4) % NP);
+    const bool term = !has_up;
+    T coup[NS][NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) coup[j][k] = T(a.coup[j][k]);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      T hv[NC];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) {
+        const T* s = sv + ((cb + i) * NC + comp) * LDP;
+        const T* gg = sg + ((cb + i) * NC + comp) * LDP;
+        const T w0 = s[iap];
+        hv[comp] = w0;
+        T f = cdel * dp2inv * (-s[ap2] + T(16) * s[ap1] - T(30) * w0 + T(16) * s[am1] - s[am2]);
+        f += dpinv * (-gg[ap2] + T(8) * gg[ap1] - T(8) * gg[am1] + gg[am2]);
+        if (term)
+          f += c0 * dpdpinv *
+               (s[am4] - T(16) * s[am3] + T(64) * s[am2] + T(16) * s[am1] - T(130) * w0 + T(16) * s[ap1] +
+                T(64) * s[ap2] - T(16) * s[ap3] + s[ap4]);
+        acc[i][comp] += f;
+      }
+      // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p
+      T cm[NC];
+      commutator_mi<NS, T>(coup, hv, cm);
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) acc[i][comp] += cm[comp];
+    }
+  }
+  __syncthreads();
+  {
+    const T coef = T(a.coef);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp)
+        sg[((cb + i) * NC + comp) * LDP + iap] = yv[i][comp] + coef * acc[i][comp];
+  }
+
+  // ---- P3..P6: potential term, in place in LDS ---------------------------
+  // Transform f takes its real part from one packed component column and its
+  // imaginary part from another.
+  auto fft_desc = [&](int f, int& colA, int& compA, int& colB, int& compB, int& kind, int& sj, int& sk) {
+    // kind 0: two real diagonal components (state sj of colA, sk of colB)
     // kind 1: off-diagonal pair (sj, sk) of column colA
     if (f < TQ) {
       colA = colB = f;
@@ -238,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
     const int c = f / NPAIR;
     const int pr = f % NPAIR;
     const int j = (pr < NS - 1) ? 0 : 1;
-    const int k = (pr == 0) ? 1 : (pr == 1 ? (NS == 2 ? 1 : 2) : 2);
+    const int k = (pr == 0) ? 1 : 2;
     colA = colB = c;
     sj = j;
     sk = k;
@@ -247,34 +268,59 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
     kind = 1;
   };
 
-  // P2: first forward pass, thread item (f, n2): N1-point DFTs over stride n2.
-  for (int it = tid; it < NFFT * N2; it += kBlock) {
+  // P3: first forward pass, item (f, n2): N1-point DFTs over stride N2.
+  for (int it = tid; it < NFFT * N2; it += NT) {
     const int f = it / N2, n2 = it % N2;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * NP;
-    T* im = sv + (colB * NC + compB) * NP;
+    T* re = sv + (colA * NC + compA) * LDP;
+    T* im = sv + (colB * NC + compB) * LDP;
     cx<T> x[N1];
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) x[n1] = {re[N2 * n1 + n2], im[N2 * n1 + n2]};
+    for (int n1 = 0; n1 < N1; ++n1) x[n1] = {re[(N2 + 1) * n1 + n2], im[(N2 + 1) * n1 + n2]};
     SmallDft<N1, 1, T>::run(x);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) {
-      const cx<T> w = stw[(n2 * k1) % NP];
-      const cx<T> y = cmul(x[k1], w);
-      re[N2 * k1 + n2] = y.re;
-      im[N2 * k1 + n2] = y.im;
+      const cx<T> y = cmul(x[k1], stw[k1 * (N2 + 1) + n2]);
+      re[(N2 + 1) * k1 + n2] = y.re;
+      im[(N2 + 1) * k1 + n2] = y.im;
     }
   }
   __syncthreads();
 
-  // P3: second forward pass, item (f, k1): contiguous N2-point DFTs.
-  for (int it = tid; it < NFFT * N1; it += kBlock) {
+  // P4: second forward pass, item (f, k1): contiguous N2-point DFTs.  The
+  // r-space multipliers that this thread needs in P5 (same item) are
+  // fetched here so their latency overlaps the DFT work.
+  constexpr int ITEMS5 = NFFT * N1;
+  constexpr int IPT5 = (ITEMS5 + NT - 1) / NT;
+  T mulA[IPT5][N2], mulB[IPT5][N2];
+  {
+    const T* __restrict__ dtab = static_cast<const T*>(a.dtab);
+    const T* __restrict__ gtab = static_cast<const T*>(a.gtab);
+    const long long tstride = (long long)nq * NP;
+#pragma unroll
+    for (int t = 0; t < IPT5; ++t) {
+      const int it = tid + t * NT;
+      const int f = (it < ITEMS5 ? it : 0) / N1, k1 = it % N1;
+      int colA, compA, colB, compB, kind, sj, sk;
+      fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+      const int qa = min(q0 + colA, nq - 1), qb = min(q0 + colB, nq - 1);
+      const T* ta = (kind == 0) ? dtab + sj * tstride + (long long)qa * NP
+                                : gtab + (sj + sk - 1) * tstride + (long long)qa * NP;
+      const T* tb = dtab + sk * tstride + (long long)qb * NP;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        mulA[t][k2] = ta[k1 + N1 * k2];
+        mulB[t][k2] = (kind == 0) ? tb[k1 + N1 * k2] : T(0);
+      }
+    }
+  }
+  for (int it = tid; it < NFFT * N1; it += NT) {
     const int f = it / N1, k1 = it % N1;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * NP + N2 * k1;
-    T* im = sv + (colB * NC + compB) * NP + N2 * k1;
+    T* re = sv + (colA * NC + compA) * LDP + (N2 + 1) * k1;
+    T* im = sv + (colB * NC + compB) * LDP + (N2 + 1) * k1;
     cx<T> x[N2];
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) x[n2] = {re[n2], im[n2]};
@@ -287,80 +333,52 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
   }
   __syncthreads();
 
-  // P4: r-space multiplication (position k2 + N2 k1 holds index m = k1 + N1 k2),
-  // then the first inverse pass over k2 and its twiddle.  Results stay in
-  // registers until every thread has read its partner values.
-  constexpr int ITEMS4 = NFFT * N1;
-  constexpr int IPT4 = (ITEMS4 + kBlock - 1) / kBlock;
-  cx<T> gbuf[IPT4][N2];
-  const T half_dr = T(0.5 * a.dr);
-  const T qlo = T(a.qlo), qhi = T(a.qhi);
-  const T inv_hbar = T(a.inv_hbar);
-  const T inv_np = T(1.0 / NP);
+  // P5: r-space multiplication (position k2 + (N2+1) k1 holds index
+  // m = k1 + N1 k2), then the first inverse pass over k2 and its twiddle;
+  // results stay in registers until every thread has read its partner values.
+  cx<T> gbuf[IPT5][N2];
 #pragma unroll
-  for (int t = 0; t < IPT4; ++t) {
-    const int it = tid + t * kBlock;
-    if (it >= ITEMS4) continue;
+  for (int t = 0; t < IPT5; ++t) {
+    const int it = tid + t * NT;
+    if (it >= ITEMS5) continue;
     const int f = it / N1, k1 = it % N1;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    const T* re = sv + (colA * NC + compA) * NP;
-    const T* im = sv + (colB * NC + compB) * NP;
-    const T qa = T(a.q0 + (q0 + colA) * a.dq);
-    const T qb = T(a.q0 + (q0 + colB) * a.dq);
+    const T* re = sv + (colA * NC + compA) * LDP;
+    const T* im = sv + (colB * NC + compB) * LDP;
     cx<T> y[N2];
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int m = k1 + N1 * k2;
-      const int mh = (m <= NP / 2) ? m : m - NP;
-      const T hr = T(mh) * half_dr;  // r/2
-      const bool nyq = (m == NP / 2);
-      const cx<T> z = {re[k2 + N2 * k1], im[k2 + N2 * k1]};
+      const cx<T> z = {re[k2 + (N2 + 1) * k1], im[k2 + (N2 + 1) * k1]};
       if (kind == 0) {
-        T dA = T(0), dB = T(0);
-        if (!nyq) {
-          dA = (poly_eval<T, NS>(a.poly, sj, clampT(qa + hr, qlo, qhi)) -
-                poly_eval<T, NS>(a.poly, sj, clampT(qa - hr, qlo, qhi))) *
-               inv_hbar;
-          dB = (poly_eval<T, NS>(a.poly, sk, clampT(qb + hr, qlo, qhi)) -
-                poly_eval<T, NS>(a.poly, sk, clampT(qb - hr, qlo, qhi))) *
-               inv_hbar;
-        }
+        // two real sequences in one transform: Y = -i [ s Z[m] + d conj(Z[-m]) ]
         const int mp = (NP - m) % NP;
-        const int pp = (mp / N1) + N2 * (mp % N1);
-        const cx<T> zp = {re[pp], -im[pp]};  // conj(Z[-m])
-        const T s = (dA + dB) * T(0.5) * inv_np, d = (dA - dB) * T(0.5) * inv_np;
-        // Y = -i [ s Z + d conj(Z[-m]) ]
-        const cx<T> u = {s * z.re + d * zp.re, s * z.im + d * zp.im};
+        const int pp = (mp / N1) + (N2 + 1) * (mp % N1);
+        const cx<T> zp = {re[pp], -im[pp]};
+        const T sA = mulA[t][k2] + mulB[t][k2], dA = mulA[t][k2] - mulB[t][k2];
+        const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
         y[k2] = {u.im, -u.re};
       } else {
-        const T xp = clampT(qa + hr, qlo, qhi), xm = clampT(qa - hr, qlo, qhi);
-        T gap;
-        if (!nyq) {
-          gap = poly_eval<T, NS>(a.poly, sj, xp) - poly_eval<T, NS>(a.poly, sk, xm);
-        } else {
-          gap = T(0.5) * (poly_eval<T, NS>(a.poly, sj, xp) + poly_eval<T, NS>(a.poly, sj, xm)) -
-                T(0.5) * (poly_eval<T, NS>(a.poly, sk, xp) + poly_eval<T, NS>(a.poly, sk, xm));
-        }
-        const T g = gap * inv_hbar * inv_np;
         // Y = -i g Z
-        y[k2] = {g * z.im, -g * z.re};
+        const T gg = mulA[t][k2];
+        y[k2] = {gg * z.im, -gg * z.re};
       }
     }
     SmallDft<N2, -1, T>::run(y);
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) gbuf[t][n2] = cmulc(y[n2], stw[(n2 * k1) % NP]);
+    for (int n2 = 0; n2 < N2; ++n2) gbuf[t][n2] = cmulc(y[n2], stw[k1 * (N2 + 1) + n2]);
   }
   __syncthreads();
 #pragma unroll
-  for (int t = 0; t < IPT4; ++t) {
-    const int it = tid + t * kBlock;
-    if (it >= ITEMS4) continue;
+  for (int t = 0; t < IPT5; ++t) {
+    const int it = tid + t * NT;
+    if (it >= ITEMS5) continue;
     const int f = it / N1, k1 = it % N1;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * NP + N2 * k1;
-    T* im = sv + (colB * NC + compB) * NP + N2 * k1;
+    T* re = sv + (colA * NC + compA) * LDP + (N2 + 1) * k1;
+    T* im = sv + (colB * NC + compB) * LDP + (N2 + 1) * k1;
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) {
       re[n2] = gbuf[t][n2].re;
@@ -369,50 +387,41 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
   }
   __syncthreads();
 
-  // P5: second inverse pass, item (f, n2): N1-point DFTs over stride n2,
+  // P6: second inverse pass, item (f, n2): N1-point DFTs over stride N2,
   // natural order out.
-  for (int it = tid; it < NFFT * N2; it += kBlock) {
+  for (int it = tid; it < NFFT * N2; it += NT) {
     const int f = it / N2, n2 = it % N2;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * NP;
-    T* im = sv + (colB * NC + compB) * NP;
+    T* re = sv + (colA * NC + compA) * LDP;
+    T* im = sv + (colB * NC + compB) * LDP;
     cx<T> x[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) x[k1] = {re[n2 + N2 * k1], im[n2 + N2 * k1]};
+    for (int k1 = 0; k1 < N1; ++k1) x[k1] = {re[n2 + (N2 + 1) * k1], im[n2 + (N2 + 1) * k1]};
     SmallDft<N1, -1, T>::run(x);
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
-      re[n2 + N2 * n1] = x[n1].re;
-      im[n2 + N2 * n1] = x[n1].im;
+      re[n2 + (N2 + 1) * n1] = x[n1].re;
+      im[n2 + (N2 + 1) * n1] = x[n1].im;
     }
   }
   __syncthreads();
 
-  // ---- P6: combine, write, level-0 trace partial -------------------------
-  T* outp = static_cast<T*>(a.out) + (long long)b * a.member_stride +
-                         (long long)n * a.level_stride;
-  const T* yp =
-      a.y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride + (long long)n * a.level_stride
-          : nullptr;
+  // ---- P7: combine, write, level-0 trace partial -------------------------
+  T* outp = static_cast<T*>(a.out) + (long long)b * a.member_stride + (long long)n * a.level_stride;
   const T coef = T(a.coef);
   const bool want_trace = (a.partials != nullptr) && (n == 0);
   double tr = 0.0;
 #pragma unroll
-  for (int t = 0; t < CPT; ++t) {
-    const int e = tid + t * kBlock;
-    if (e >= CELLS) continue;
-    const int c = e / NP;
-    const int ia = e % NP;
-    const int q = q0 + c;
+  for (int i = 0; i < CPT; ++i) {
+    const int q = q0 + cb + i;
     if (q >= nq) continue;
     T o[NC];
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
-      const long long idx = comp * cs + (long long)q * NP + ia;
-      const T base = yp ? yp[idx] : T(0);
-      o[comp] = base + coef * (acc[t][comp] + sv[(c * NC + comp) * NP + ia]);
-      outp[idx] = o[comp];
+      const int li = ((cb + i) * NC + comp) * LDP + iap;
+      o[comp] = sg[li] + coef * sv[li];
+      outp[comp * cs + (long long)q * NP + ia] = o[comp];
     }
     if (want_trace) {
 #pragma unroll
@@ -420,19 +429,19 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(StageArgs a) {
 #pragma unroll
       for (int j = 0; j < NS; ++j)
 #pragma unroll
-        for (int k = j + 1; k < NS; ++k)
-          tr += 2.0 * a.mu[j][k] * (double)o[Packing<NS>::re(j, k)];
+        for (int k = j + 1; k < NS; ++k) tr += 2.0 * a.mu[j][k] * (double)o[Packing<NS>::re(j, k)];
     }
   }
   if (want_trace) {
-    // deterministic workgroup sum: wave butterfly, then fixed-order over waves
-    __shared__ double wsum[kBlock / 64];
+    // deterministic workgroup sum: wave butterfly, then fixed order over waves
+    constexpr int NW = (NT + 63) / 64;
+    __shared__ double wsum[NW];
     for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
     if ((tid & 63) == 0) wsum[tid >> 6] = tr;
     __syncthreads();
     if (tid == 0) {
       double s = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+      for (int w = 0; w < NW; ++w) s += wsum[w];
       a.partials[((long long)b * kRespSlots + a.slot) * a.ntiles + tile] = s;
     }
   }
@@ -443,7 +452,7 @@ hipError_t launch_stage(int np, const StageArgs& a, int nblocks, hipStream_t s) 
   switch (np) {
 #define QHFPE_CASE(NP_)                                                             \
   case NP_:                                                                         \
-    hipLaunchKernelGGL((stage_kernel<T, NS, NP_>), dim3(nblocks), dim3(kBlock), 0, s, a); \
+    hipLaunchKernelGGL((stage_kernel<T, NS, NP_>), dim3(nblocks), dim3(PlanOf<T, NS, NP_>::NT), 0, s, a); \
     return hipGetLastError();
     QHFPE_CASE(8)
     QHFPE_CASE(12)

@@ -215,3 +215,24 @@ def test_third_order_response_protocol_small():
     tr = C.step(n3, 2).cpu().numpy().reshape(len(t2s), len(t1s), -1)
     got = (1j) ** 3 * tr
     assert rel(got, ref) < 1e-11
+
+
+def test_member_bath_sweep_matches_separate_runs():
+    """Members with different zeta/gamma/beta in one batch equal separate runs bitwise."""
+    d = small_model(nq=20, np_=32, depth=3)
+    baths = [(0.1, 1.0, 1.0), (1.0, 0.7, 0.5), (2.0, 1.5, 2.0)]
+    P = qhfpe.Propagator(d, batch=3)
+    for i, (z, g, bt) in enumerate(baths):
+        P.set_member_bath(i, z, g, bt)
+    P.init_thermal(1.0)
+    P.apply_dipole()
+    r = P.step(30, 3).cpu().numpy()
+    for i, (z, g, bt) in enumerate(baths):
+        di = inputs.model_dict(d, zeta=z, gamma=g, beta=bt)
+        Q = qhfpe.Propagator(di, batch=1)
+        Q.init_thermal(1.0)
+        Q.apply_dipole()
+        np.testing.assert_array_equal(Q.step(30, 3).cpu().numpy()[0], r[i])
+        m = oracle_model(di)
+        _, ref = O.propagate(m, O.dipole_commutator(m, O.thermal_initial_state(m, 1.0)), 30, 3)
+        assert rel(r[i], ref) < 1e-11
