@@ -44,7 +44,7 @@ struct Layout {
   long long member_elems = 0, level_elems = 0, comp_elems = 0;
   size_t state_bytes = 0;
   size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
-  size_t off_dtab = 0, off_gtab = 0, off_bath = 0;
+  size_t off_dtab = 0, off_gtab = 0, off_bath = 0, off_psym = 0;
   int n1 = 0, n2 = 0;
   size_t total = 0;
   size_t red_count = 0;
@@ -123,6 +123,8 @@ Layout make_layout(const qhfpe_params* p) {
   off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
   L.off_bath = off;
   off += align_up((size_t)p->batch * kBathStride * sizeof(double));
+  L.off_psym = off;
+  off += align_up((size_t)2 * p->np * L.elem);
   L.off_flag = off;
   off += kAlign;
   L.total = off;
@@ -182,6 +184,22 @@ void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<
   }
 }
 
+// Symbols of the periodic fourth-order p-stencils in the DFT convention
+// rho~[m] = sum_a W[a] exp(+2 pi i a m / np): a stencil sum_k c_k W[a + k]
+// multiplies rho~[m] by sum_k c_k exp(-i k theta), theta = 2 pi m / np.
+//   D_p2:      (-30 + 32 cos theta - 2 cos 2 theta) / (12 dp^2)
+//   D_p D_p:  -(16 sin theta - 2 sin 2 theta)^2 / (144 dp^2)
+// Both are stored divided by np (the inverse-transform normalisation).
+void stencil_symbols(int np, double dp, std::vector<double>& sym) {
+  sym.assign(2 * (size_t)np, 0.0);
+  for (int m = 0; m < np; ++m) {
+    const double th = 2.0 * M_PI * (double)m / (double)np;
+    const double s1 = 16.0 * std::sin(th) - 2.0 * std::sin(2.0 * th);
+    sym[m] = (-30.0 + 32.0 * std::cos(th) - 2.0 * std::cos(2.0 * th)) / (12.0 * dp * dp) / np;
+    sym[np + m] = -(s1 * s1) / (144.0 * dp * dp) / np;
+  }
+}
+
 // n1 x (n2 + 1) padded table of exp(+2 pi i (n2 k1 mod np) / np)
 void twiddle_table(int np, int n1, int n2, std::vector<double>& tw) {
   tw.assign((size_t)n1 * (n2 + 1) * 2, 0.0);
@@ -218,6 +236,7 @@ struct qhfpe_handle {
   void* dtab() const { return ws + L.off_dtab; }
   void* gtab() const { return ws + L.off_gtab; }
   double* bath() const { return reinterpret_cast<double*>(ws + L.off_bath); }
+  void* psym() const { return ws + L.off_psym; }
   int* flag() const { return reinterpret_cast<int*>(ws + L.off_flag); }
 
   GridDesc grid() const {
@@ -245,6 +264,7 @@ struct qhfpe_handle {
     a.dtab = dtab();
     a.gtab = gtab();
     a.bath = bath();
+    a.psym = psym();
     a.slot = 0;
     a.nq = p.nq;
     a.depth = p.depth;
@@ -351,8 +371,9 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
   // setup tables, computed in FP64 and rounded once to the state precision
-  std::vector<double> tw, dt, gt;
+  std::vector<double> tw, dt, gt, sym;
   twiddle_table(params->np, L.n1, L.n2, tw);
+  stencil_symbols(params->np, h->dp, sym);
   multiplier_tables(*params, h->dq, h->dp, dt, gt);
   std::vector<double> bath((size_t)params->batch * kBathStride);
   double bc[kBathStride];
@@ -373,6 +394,7 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   up(h->twiddle(), tw);
   up(h->dtab(), dt);
   up(h->gtab(), gt);
+  up(h->psym(), sym);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bath(), bath.data(), bath.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->y(), 0, 3 * L.state_bytes, h->stream);

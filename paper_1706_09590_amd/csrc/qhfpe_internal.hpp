@@ -46,6 +46,7 @@ struct StageArgs {
   const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
   const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
+  const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
   int slot;
   int nq;
   int depth;

@@ -72,7 +72,7 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nblocks) {
 }
 
 template <typename T, int NS, int NP>
-__global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArgs a) {
+__global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(StageArgs a) {
   using P = PlanOf<T, NS, NP>;
   constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ, NT = P::NT, CPT = P::CPT;
   constexpr int NC = NS * NS;
@@ -84,11 +84,15 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
 
   // LDS columns are padded by one element per N2 block (index a + a / N2),
   // so the FFT passes that walk a column with stride N2 are free of bank
-  // conflicts.
-  constexpr int LDP = NP + NP / N2;
+  // conflicts; the column stride is then rounded to 4 (mod 16) elements so
+  // that the transforms of neighbouring columns, which share a wave, start
+  // on different banks.
+  constexpr int LDP0 = NP + NP / N2;
+  constexpr int LDP = (NP >= 64) ? LDP0 + ((4 - LDP0 % 16) + 16) % 16 : LDP0;
   __shared__ T sv[TQ * NC * LDP];   // v^(n) tile, then the potential term in place
   __shared__ T sg[TQ * NC * LDP];   // field differentiated once along p, then y + coef * local terms
   __shared__ cx<T> stw[N1 * (N2 + 1)];  // w^(n2 k1), row k1 padded to N2 + 1
+  __shared__ T ssym[2 * NP];            // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
 
   const int nblocks = a.ntiles * (a.depth + 1) * a.batch;
   const int lb = xcd_logical_block(blockIdx.x, a.nblocks_padded);
@@ -104,17 +108,19 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
   const int ia = tid % NP;           // this thread's p node
   const int iap = ia + ia / N2;      // its padded LDS index
   const int cb = (tid / NP) * CPT;   // first of its CPT tile columns
-  const long long cs = a.comp_stride;
+  const unsigned cs = (unsigned)a.comp_stride;
 
-  const T* __restrict__ v = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
-  const T* __restrict__ vn = v + (long long)n * a.level_stride;
+  // uniform base pointers of this member and level; per-thread offsets are 32-bit
+  const T* __restrict__ vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
+  const T* __restrict__ vn = vm + (long long)n * a.level_stride;
   const bool has_up = n < a.depth, has_dn = n >= 1;
-  const T* __restrict__ vu = v + (long long)(has_up ? n + 1 : n) * a.level_stride;
-  const T* __restrict__ vd = v + (long long)(has_dn ? n - 1 : n) * a.level_stride;
+  const T* __restrict__ vu = vm + (long long)(has_up ? n + 1 : n) * a.level_stride;
+  const T* __restrict__ vd = vm + (long long)(has_dn ? n - 1 : n) * a.level_stride;
   const T* yp = a.y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride + (long long)n * a.level_stride
                     : nullptr;
 
   for (int j = tid; j < N1 * (N2 + 1); j += NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
+  for (int j = tid; j < 2 * NP; j += NT) ssym[j] = static_cast<const T*>(a.psym)[j];
 
   const T p = T(a.p0 + ia * a.dp);
   const double* bath = a.bath + kBathStride * b;
@@ -135,30 +141,34 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
   }
 
   // ---- P1: all global loads of this thread, then local terms -------------
+  // offsets of this thread's p node in the q columns cb-3 .. cb+CPT+2
+  // (clamped to the grid; out-of-grid values are masked to zero)
   T acc[CPT][NC];
-  T yv[CPT][NC];
-  int qc[CPT + 6];
+  unsigned qo[CPT + 6];
   bool qin[CPT + 6];
 #pragma unroll
   for (int j = 0; j < CPT + 6; ++j) {
     const int q = q0 + cb + j - 3;
     qin[j] = (q >= 0) && (q < nq);
-    qc[j] = q < 0 ? 0 : (q >= nq ? nq - 1 : q);
+    qo[j] = (unsigned)(q < 0 ? 0 : (q >= nq ? nq - 1 : q)) * NP + ia;
   }
+  // components are processed in groups of LGRP; the scheduling barrier keeps
+  // the next group's loads from being hoisted, which bounds register use
+  constexpr int LGRP = (sizeof(T) == 8) ? 1 : 2;
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
-    const long long co = comp * cs + ia;
+    if (comp % LGRP == 0 && comp > 0) __builtin_amdgcn_sched_barrier(0);
+    const unsigned co = comp * cs;
     T w[CPT + 6];
 #pragma unroll
-    for (int j = 0; j < CPT + 6; ++j) w[j] = vn[co + (long long)qc[j] * NP];
+    for (int j = 0; j < CPT + 6; ++j) w[j] = vn[co + qo[j]];
 #pragma unroll
     for (int j = 0; j < CPT + 6; ++j) w[j] = qin[j] ? w[j] : T(0);
     T up[CPT], dn[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-      up[i] = vu[co + (long long)qc[i + 3] * NP];
-      dn[i] = vd[co + (long long)qc[i + 3] * NP];
-      yv[i][comp] = yp ? yp[co + (long long)qc[i + 3] * NP] : T(0);
+      up[i] = vu[co + qo[i + 3]];
+      dn[i] = vd[co + qo[i + 3]];
     }
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -179,19 +189,28 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
       sg[((cb + i) * NC + comp) * LDP + iap] = qin[i + 3] ? g : T(0);
     }
   }
+  // materialise the local terms here: otherwise their arithmetic is sunk to
+  // the parking step and every loaded q-window stays live across the barriers
+#pragma unroll
+  for (int i = 0; i < CPT; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) asm volatile("" : "+v"(acc[i][comp]));
   __syncthreads();
 
-  // ---- P2: p-stencils and the pointwise coupling commutator ---------------
+  // ---- P2: D_p of the level-coupling field and the coupling commutator ----
+  // (the periodic p-stencils acting on v^(n) itself, c_delta D_p2 and the
+  // terminator's c0 D_p D_p, are applied in the DFT domain in P5).  The RK
+  // base state y is fetched first so that its latency overlaps this phase.
+  T yv[CPT][NC];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) yv[i][comp] = yp ? yp[comp * cs + qo[i + 3]] : T(0);
   {
     const T dpinv = T(1.0 / (12.0 * a.dp));
-    const T dp2inv = T(1.0 / (12.0 * a.dp * a.dp));
-    const T dpdpinv = T(1.0 / (144.0 * a.dp * a.dp));
     auto pd = [](int x) { return x + x / N2; };
     const int am1 = pd((ia + NP - 1) % NP), am2 = pd((ia + NP - 2) % NP);
     const int ap1 = pd((ia + 1) % NP), ap2 = pd((ia + 2) % NP);
-    const int am3 = pd((ia + NP - 3) % NP), am4 = pd((ia + NP - 4) % NP);
-    const int ap3 = pd((ia + 3) % NP), ap4 = pd((ia + 4) % NP);
-    const bool term = !has_up;
     T coup[NS][NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
@@ -202,17 +221,9 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
       T hv[NC];
 #pragma unroll
       for (int comp = 0; comp < NC; ++comp) {
-        const T* s = sv + ((cb + i) * NC + comp) * LDP;
         const T* gg = sg + ((cb + i) * NC + comp) * LDP;
-        const T w0 = s[iap];
-        hv[comp] = w0;
-        T f = cdel * dp2inv * (-s[ap2] + T(16) * s[ap1] - T(30) * w0 + T(16) * s[am1] - s[am2]);
-        f += dpinv * (-gg[ap2] + T(8) * gg[ap1] - T(8) * gg[am1] + gg[am2]);
-        if (term)
-          f += c0 * dpdpinv *
-               (s[am4] - T(16) * s[am3] + T(64) * s[am2] + T(16) * s[am1] - T(130) * w0 + T(16) * s[ap1] +
-                T(64) * s[ap2] - T(16) * s[ap3] + s[ap4]);
-        acc[i][comp] += f;
+        hv[comp] = sv[((cb + i) * NC + comp) * LDP + iap];
+        acc[i][comp] += dpinv * (-gg[ap2] + T(8) * gg[ap1] - T(8) * gg[am1] + gg[am2]);
       }
       // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p
       T cm[NC];
@@ -223,6 +234,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
   }
   __syncthreads();
   {
+    // park y + coef * (local terms) in sg, which P2 no longer needs
     const T coef = T(a.coef);
 #pragma unroll
     for (int i = 0; i < CPT; ++i)
@@ -269,7 +281,11 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
   };
 
   // P3: first forward pass, item (f, n2): N1-point DFTs over stride N2.
-  for (int it = tid; it < NFFT * N2; it += NT) {
+  constexpr int ITEMS3 = NFFT * N2;
+#pragma unroll
+  for (int t = 0; t < (ITEMS3 + NT - 1) / NT; ++t) {
+    const int it = tid + t * NT;
+    if (it >= ITEMS3) continue;
     const int f = it / N2, n2 = it % N2;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
@@ -315,7 +331,10 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
       }
     }
   }
-  for (int it = tid; it < NFFT * N1; it += NT) {
+#pragma unroll
+  for (int t = 0; t < IPT5; ++t) {
+    const int it = tid + t * NT;
+    if (it >= ITEMS5) continue;
     const int f = it / N1, k1 = it % N1;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
@@ -337,6 +356,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
   // m = k1 + N1 k2), then the first inverse pass over k2 and its twiddle;
   // results stay in registers until every thread has read its partner values.
   cx<T> gbuf[IPT5][N2];
+  const T c0t = has_up ? T(0) : c0;  // terminator level carries c0 D_p D_p
 #pragma unroll
   for (int t = 0; t < IPT5; ++t) {
     const int it = tid + t * NT;
@@ -351,6 +371,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
     for (int k2 = 0; k2 < N2; ++k2) {
       const int m = k1 + N1 * k2;
       const cx<T> z = {re[k2 + (N2 + 1) * k1], im[k2 + (N2 + 1) * k1]};
+      // real, even symbol of the p-stencils that act on v^(n) in every component
+      const T e = cdel * ssym[m] + c0t * ssym[NP + m];
       if (kind == 0) {
         // two real sequences in one transform: Y = -i [ s Z[m] + d conj(Z[-m]) ]
         const int mp = (NP - m) % NP;
@@ -358,11 +380,11 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
         const cx<T> zp = {re[pp], -im[pp]};
         const T sA = mulA[t][k2] + mulB[t][k2], dA = mulA[t][k2] - mulB[t][k2];
         const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
-        y[k2] = {u.im, -u.re};
+        y[k2] = {u.im + e * z.re, -u.re + e * z.im};
       } else {
         // Y = -i g Z
         const T gg = mulA[t][k2];
-        y[k2] = {gg * z.im, -gg * z.re};
+        y[k2] = {gg * z.im + e * z.re, -gg * z.re + e * z.im};
       }
     }
     SmallDft<N2, -1, T>::run(y);
@@ -389,7 +411,10 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
 
   // P6: second inverse pass, item (f, n2): N1-point DFTs over stride N2,
   // natural order out.
-  for (int it = tid; it < NFFT * N2; it += NT) {
+#pragma unroll
+  for (int t = 0; t < (ITEMS3 + NT - 1) / NT; ++t) {
+    const int it = tid + t * NT;
+    if (it >= ITEMS3) continue;
     const int f = it / N2, n2 = it % N2;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
@@ -421,7 +446,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT)) stage_kernel(StageArg
     for (int comp = 0; comp < NC; ++comp) {
       const int li = ((cb + i) * NC + comp) * LDP + iap;
       o[comp] = sg[li] + coef * sv[li];
-      outp[comp * cs + (long long)q * NP + ia] = o[comp];
+      outp[comp * cs + (unsigned)q * NP + ia] = o[comp];
     }
     if (want_trace) {
 #pragma unroll
