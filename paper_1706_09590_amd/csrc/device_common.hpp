@@ -171,6 +171,36 @@ struct SmallDft {
 };
 
 // ---------------------------------------------------------------------------
+// Buffer-resource memory access: a 32-bit per-lane byte offset (voffset)
+// plus a wave-uniform byte offset (soffset) from a uniform base, with the
+// hardware range check of raw buffers (reads past num_records return 0,
+// writes past it are dropped).
+// ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufferDword3 = 0x00020000;  // raw buffer, gfx9-family data format bits
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufferDword3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, rsrc_t r, unsigned voff, unsigned soff) {
+  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Hermitian-packed electronic matrices.  Component order: diagonal j at j;
 // off-diagonal pair (j, k), j < k, at NS + 2 * pair(j, k) (re) and +1 (im),
 // pairs enumerated (0,1), (0,2), (1,2).

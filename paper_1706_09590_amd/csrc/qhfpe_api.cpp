@@ -84,6 +84,9 @@ int validate(const qhfpe_params* p) {
     }
   const long double elems = (long double)p->batch * (p->depth + 1) * ns * ns * p->nq * p->np;
   if (elems > 4.0e11L) return fail(QHFPE_EINVAL, "state too large");
+  // one hierarchy level of one member is addressed with 32-bit byte offsets
+  const long double level_bytes = (long double)ns * ns * p->nq * p->np * 8.0L;
+  if (level_bytes >= 2147483648.0L) return fail(QHFPE_EUNSUPPORTED, "one level exceeds 2 GiB");
   return QHFPE_OK;
 }
 

@@ -110,14 +110,21 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
   const int cb = (tid / NP) * CPT;   // first of its CPT tile columns
   const unsigned cs = (unsigned)a.comp_stride;
 
-  // uniform base pointers of this member and level; per-thread offsets are 32-bit
-  const T* __restrict__ vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
-  const T* __restrict__ vn = vm + (long long)n * a.level_stride;
+  // buffer resources over whole levels of this member: the per-lane byte
+  // offset addresses (q, p), the uniform soffset selects the component
+  constexpr unsigned ES = sizeof(T);
+  const unsigned level_bytes = (unsigned)(a.level_stride * ES);
+  const T* vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
   const bool has_up = n < a.depth, has_dn = n >= 1;
-  const T* __restrict__ vu = vm + (long long)(has_up ? n + 1 : n) * a.level_stride;
-  const T* __restrict__ vd = vm + (long long)(has_dn ? n - 1 : n) * a.level_stride;
-  const T* yp = a.y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride + (long long)n * a.level_stride
-                    : nullptr;
+  const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);
+  const rsrc_t ru = make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, level_bytes);
+  const rsrc_t rd = make_rsrc(vm + (long long)(has_dn ? n - 1 : n) * a.level_stride, level_bytes);
+  const bool has_y = a.y != nullptr;
+  const rsrc_t ry = make_rsrc(has_y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride +
+                                          (long long)n * a.level_stride
+                                    : vm,
+                              has_y ? level_bytes : 0u);
+  const unsigned cbytes = cs * ES;   // soffset step per packed component
 
   for (int j = tid; j < N1 * (N2 + 1); j += NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
   for (int j = tid; j < 2 * NP; j += NT) ssym[j] = static_cast<const T*>(a.psym)[j];
@@ -141,16 +148,18 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
   }
 
   // ---- P1: all global loads of this thread, then local terms -------------
-  // offsets of this thread's p node in the q columns cb-3 .. cb+CPT+2
-  // (clamped to the grid; out-of-grid values are masked to zero)
+  // byte offsets of this thread's p node in the q columns cb-3 .. cb+CPT+2,
+  // clamped to the grid; tiles that touch the q edges mask the ghost
+  // columns to zero (a uniform branch)
   T acc[CPT][NC];
   unsigned qo[CPT + 6];
   bool qin[CPT + 6];
+  const bool edge = (q0 - 3 < 0) || (q0 + TQ + 3 > nq);
 #pragma unroll
   for (int j = 0; j < CPT + 6; ++j) {
     const int q = q0 + cb + j - 3;
     qin[j] = (q >= 0) && (q < nq);
-    qo[j] = (unsigned)(q < 0 ? 0 : (q >= nq ? nq - 1 : q)) * NP + ia;
+    qo[j] = ((unsigned)(q < 0 ? 0 : (q >= nq ? nq - 1 : q)) * NP + ia) * ES;
   }
   // components are processed in groups of LGRP; the scheduling barrier keeps
   // the next group's loads from being hoisted, which bounds register use
@@ -158,17 +167,19 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     if (comp % LGRP == 0 && comp > 0) __builtin_amdgcn_sched_barrier(0);
-    const unsigned co = comp * cs;
+    const unsigned so = comp * cbytes;
     T w[CPT + 6];
 #pragma unroll
-    for (int j = 0; j < CPT + 6; ++j) w[j] = vn[co + qo[j]];
+    for (int j = 0; j < CPT + 6; ++j) w[j] = buf_load<T>(rn, qo[j], so);
+    if (edge) {
 #pragma unroll
-    for (int j = 0; j < CPT + 6; ++j) w[j] = qin[j] ? w[j] : T(0);
+      for (int j = 0; j < CPT + 6; ++j) w[j] = qin[j] ? w[j] : T(0);
+    }
     T up[CPT], dn[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-      up[i] = vu[co + qo[i + 3]];
-      dn[i] = vd[co + qo[i + 3]];
+      up[i] = buf_load<T>(ru, qo[i + 3], so);
+      dn[i] = buf_load<T>(rd, qo[i + 3], so);
     }
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -186,7 +197,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
       }
       acc[i][comp] = f;
       sv[((cb + i) * NC + comp) * LDP + iap] = w0;
-      sg[((cb + i) * NC + comp) * LDP + iap] = qin[i + 3] ? g : T(0);
+      sg[((cb + i) * NC + comp) * LDP + iap] = (!edge || qin[i + 3]) ? g : T(0);
     }
   }
   // materialise the local terms here: otherwise their arithmetic is sunk to
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
 #pragma unroll
   for (int i = 0; i < CPT; ++i)
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) yv[i][comp] = yp ? yp[comp * cs + qo[i + 3]] : T(0);
+    for (int comp = 0; comp < NC; ++comp) yv[i][comp] = buf_load<T>(ry, qo[i + 3], comp * cbytes);
   {
     const T dpinv = T(1.0 / (12.0 * a.dp));
     auto pd = [](int x) { return x + x / N2; };
@@ -311,9 +322,9 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
   constexpr int IPT5 = (ITEMS5 + NT - 1) / NT;
   T mulA[IPT5][N2], mulB[IPT5][N2];
   {
-    const T* __restrict__ dtab = static_cast<const T*>(a.dtab);
-    const T* __restrict__ gtab = static_cast<const T*>(a.gtab);
-    const long long tstride = (long long)nq * NP;
+    const unsigned tbytes = (unsigned)((long long)nq * NP * ES);  // one multiplier table
+    const rsrc_t rdt = make_rsrc(a.dtab, NS * tbytes);
+    const rsrc_t rgt = make_rsrc(a.gtab, NPAIR * tbytes);
 #pragma unroll
     for (int t = 0; t < IPT5; ++t) {
       const int it = tid + t * NT;
@@ -321,13 +332,16 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
       int colA, compA, colB, compB, kind, sj, sk;
       fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
       const int qa = min(q0 + colA, nq - 1), qb = min(q0 + colB, nq - 1);
-      const T* ta = (kind == 0) ? dtab + sj * tstride + (long long)qa * NP
-                                : gtab + (sj + sk - 1) * tstride + (long long)qa * NP;
-      const T* tb = dtab + sk * tstride + (long long)qb * NP;
+      const unsigned oa = ((unsigned)qa * NP + k1) * ES, ob = ((unsigned)qb * NP + k1) * ES;
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
-        mulA[t][k2] = ta[k1 + N1 * k2];
-        mulB[t][k2] = (kind == 0) ? tb[k1 + N1 * k2] : T(0);
+        if (kind == 0) {
+          mulA[t][k2] = buf_load<T>(rdt, oa + N1 * k2 * ES, sj * tbytes);
+          mulB[t][k2] = buf_load<T>(rdt, ob + N1 * k2 * ES, sk * tbytes);
+        } else {
+          mulA[t][k2] = buf_load<T>(rgt, oa + N1 * k2 * ES, (sj + sk - 1) * tbytes);
+          mulB[t][k2] = T(0);
+        }
       }
     }
   }
@@ -349,6 +363,12 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
       re[k2] = x[k2].re;
       im[k2] = x[k2].im;
     }
+    // block 0 also stores X[0] in its padding slot, so that the partner of
+    // index m lies at base - k2 for every block (see P5)
+    if (k1 == 0) {
+      re[N2] = x[0].re;
+      im[N2] = x[0].im;
+    }
   }
   __syncthreads();
 
@@ -366,18 +386,23 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
     const T* re = sv + (colA * NC + compA) * LDP;
     const T* im = sv + (colB * NC + compB) * LDP;
+    const T* zr = re + (N2 + 1) * k1;
+    const T* zi = im + (N2 + 1) * k1;
+    // partner -m of m = k1 + N1 k2 sits at position pbase - k2 (block
+    // N1 - k1 read backwards; block 0 pairs within itself via its padding copy)
+    const int pbase = (k1 == 0) ? N2 : (N2 - 1) + (N2 + 1) * (N1 - k1);
+    const T* pr = re + pbase;
+    const T* pi = im + pbase;
+    const T* sy = ssym + k1;
     cx<T> y[N2];
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
-      const int m = k1 + N1 * k2;
-      const cx<T> z = {re[k2 + (N2 + 1) * k1], im[k2 + (N2 + 1) * k1]};
+      const cx<T> z = {zr[k2], zi[k2]};
       // real, even symbol of the p-stencils that act on v^(n) in every component
-      const T e = cdel * ssym[m] + c0t * ssym[NP + m];
+      const T e = cdel * sy[N1 * k2] + c0t * sy[NP + N1 * k2];
       if (kind == 0) {
         // two real sequences in one transform: Y = -i [ s Z[m] + d conj(Z[-m]) ]
-        const int mp = (NP - m) % NP;
-        const int pp = (mp / N1) + (N2 + 1) * (mp % N1);
-        const cx<T> zp = {re[pp], -im[pp]};
+        const cx<T> zp = {pr[-k2], -pi[-k2]};
         const T sA = mulA[t][k2] + mulB[t][k2], dA = mulA[t][k2] - mulB[t][k2];
         const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
         y[k2] = {u.im + e * z.re, -u.re + e * z.im};
@@ -433,7 +458,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
   __syncthreads();
 
   // ---- P7: combine, write, level-0 trace partial -------------------------
-  T* outp = static_cast<T*>(a.out) + (long long)b * a.member_stride + (long long)n * a.level_stride;
+  const rsrc_t ro = make_rsrc(static_cast<T*>(a.out) + (long long)b * a.member_stride + (long long)n * a.level_stride,
+                              level_bytes);
   const T coef = T(a.coef);
   const bool want_trace = (a.partials != nullptr) && (n == 0);
   double tr = 0.0;
@@ -446,7 +472,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
     for (int comp = 0; comp < NC; ++comp) {
       const int li = ((cb + i) * NC + comp) * LDP + iap;
       o[comp] = sg[li] + coef * sv[li];
-      outp[comp * cs + (unsigned)q * NP + ia] = o[comp];
+      buf_store(o[comp], ro, qo[i + 3], comp * cbytes);
     }
     if (want_trace) {
 #pragma unroll
