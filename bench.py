@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--two-d", action="store_true",
+                    help="also time the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
+    ap.add_argument("--two-d-scale", type=int, default=1,
+                    help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -205,10 +209,44 @@ def main():
             errs.append(float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64))))
         line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
+    if args.two_d:
+        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(inputs.model_dict(base, zeta=1.0))
         line["cpu_baseline"] = cb
     print(json.dumps(line, default=float))
+
+
+def two_d_spectrum(scale: int = 1):
+    """Wall time of the batched 2D correlation spectrum: FP64 equilibration of
+    the 128x128 depth-6 hierarchy (reported apart), then t1 / t2 preparation
+    and all t3 propagations as one batch (FP32 state, FP64 traces), and the
+    correlation and transient-absorption spectra on [0, 20]^2 (step 0.05)."""
+    import torch
+
+    from paper_1706_09590_amd import inputs, response
+    w = inputs.TWO_D_SPECTRUM
+    m = w["model"]
+    t1s = w["t1_steps"][:: scale]
+    t2s = w["t2_steps"][:: scale]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W_eq, steps, res = response.equilibrate(m, tol=1e-10, max_steps=100000, check_every=500)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    R3 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp32")
+    om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
+    dt = m["dt"]
+    Ic = response.correlation_spectra(R3, (t1s[1] - t1s[0]) * dt, w["stride3"] * dt, om, om)
+    It = response.transient_absorption(R3, w["stride3"] * dt, om)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cells = (m["depth"] + 1) * m["nq"] * m["np"]
+    prep = sum(t1s[-1:]) + len(t1s) * t2s[-1]
+    updates = cells * (len(t1s) * len(t2s) * w["n3_steps"] + prep)
+    return dict(wall_s=t2 - t1, equilibration_s=t1 - t0, equilibration_steps=steps, equilibration_residual=res,
+                n_t1=len(t1s), n_t2=len(t2s), n3_steps=w["n3_steps"], cell_updates=updates,
+                cell_updates_per_s=updates / (t2 - t1), finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
 
 
 if __name__ == "__main__":

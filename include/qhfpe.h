@@ -112,6 +112,19 @@ int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
  * applies.  Synchronous. */
 int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta);
 
+/* Tile variant of the fused RK stage: each thread of a stage workgroup owns
+ * cells_per_thread consecutive q columns (2 or 4; 0 = default).  Variants
+ * compute the same operations per cell; results agree to rounding (the
+ * compiled instruction order and the grouping of the trace partial sums
+ * differ).  QHFPE_EUNSUPPORTED if the variant does not exist for this
+ * precision and state count. */
+int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread);
+
+/* Pick the fastest tile variant for this handle by timing reps stage launches
+ * of each (they read the state and write scratch only; the state is not
+ * changed).  h_chosen (may be NULL) receives the variant.  Synchronous. */
+int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen);
+
 /* Initial state (Sec. III protocol; harmonic thermal Wigner function):
  * W^(0)_00(p, q) = tanh(b)/(pi hbar) exp(-tanh(b) [p^2/(m hbar omega) + m omega q^2/hbar]),
  * b = beta hbar omega/2 with each member's beta, plus d_noise[i][a] (FP64

@@ -48,7 +48,7 @@ struct Layout {
   int n1 = 0, n2 = 0;
   size_t total = 0;
   size_t red_count = 0;
-  int tq = 0, ntiles = 0;
+  int max_tiles = 0;  // tiles per level at the narrowest tile variant
 };
 
 int validate(const qhfpe_params* p) {
@@ -99,8 +99,8 @@ Layout make_layout(const qhfpe_params* p) {
   L.level_elems = L.comp_elems * nc;
   L.member_elems = L.level_elems * (p->depth + 1);
   L.state_bytes = align_up((size_t)L.member_elems * p->batch * L.elem);
-  L.tq = plan_tq(p->np, (int)L.elem, p->n_states);
-  L.ntiles = (p->nq + L.tq - 1) / L.tq;
+  const int min_tq = plan_groups(p->np) * kMinCpt;
+  L.max_tiles = (p->nq + min_tq - 1) / min_tq;
   const long long cells = (long long)(p->depth + 1) * p->nq * p->np;
   const long long pack_blocks = (cells + kBlock - 1) / kBlock;
   L.red_count = (size_t)p->batch * (size_t)std::max<long long>(2 * pack_blocks, 1024);
@@ -112,7 +112,7 @@ Layout make_layout(const qhfpe_params* p) {
   L.off_vb = off;
   off += L.state_bytes;
   L.off_partials = off;
-  off += align_up((size_t)p->batch * kRespSlots * L.ntiles * sizeof(double));
+  off += align_up((size_t)p->batch * kRespSlots * L.max_tiles * sizeof(double));
   L.off_red = off;
   off += align_up(L.red_count * sizeof(double));
   L.n1 = pl->n1;
@@ -228,6 +228,10 @@ struct qhfpe_handle {
   hipStream_t stream = nullptr;
   int phase = 0;
   int ns = 0, nc = 0, levels = 0;
+  int cpt = 4;  // stage tile variant (cells per thread along q)
+
+  int tq() const { return plan_groups(p.np) * cpt; }
+  int ntiles() const { return (p.nq + tq() - 1) / tq(); }
   double dq = 0, dp = 0;
 
   void* y() const { return ws + L.off_y; }
@@ -271,9 +275,9 @@ struct qhfpe_handle {
     a.slot = 0;
     a.nq = p.nq;
     a.depth = p.depth;
-    a.ntiles = L.ntiles;
+    a.ntiles = ntiles();
     a.batch = p.batch;
-    a.nblocks_padded = (L.ntiles * levels * p.batch + 7) / 8 * 8;
+    a.nblocks_padded = (ntiles() * levels * p.batch + 7) / 8 * 8;
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;
@@ -293,8 +297,10 @@ struct qhfpe_handle {
   hipError_t launch(const StageArgs& a) const {
     const int nblocks = a.nblocks_padded;
     if (p.precision == QHFPE_FP64)
-      return ns == 2 ? launch_stage_f64_ns2(p.np, a, nblocks, stream) : launch_stage_f64_ns3(p.np, a, nblocks, stream);
-    return ns == 2 ? launch_stage_f32_ns2(p.np, a, nblocks, stream) : launch_stage_f32_ns3(p.np, a, nblocks, stream);
+      return ns == 2 ? launch_stage_f64_ns2(p.np, cpt, a, nblocks, stream)
+                     : launch_stage_f64_ns3(p.np, cpt, a, nblocks, stream);
+    return ns == 2 ? launch_stage_f32_ns2(p.np, cpt, a, nblocks, stream)
+                   : launch_stage_f32_ns3(p.np, cpt, a, nblocks, stream);
   }
 };
 
@@ -307,12 +313,12 @@ int check_handle(const qhfpe_t* h) {
 
 // partial sums of the level-0 trace of y into slot, then (optionally) finalise
 int trace_into(qhfpe_t* h, int slot) {
-  HIP_TRY(launch_trace_partials(h->grid(), h->y(), h->p.mu, h->L.tq, h->L.ntiles, h->partials(), slot, h->stream));
+  HIP_TRY(launch_trace_partials(h->grid(), h->y(), h->p.mu, h->tq(), h->ntiles(), h->partials(), slot, h->stream));
   return QHFPE_OK;
 }
 
 int finalize(qhfpe_t* h, int nslots, double* resp, long long resp_stride, long long offset) {
-  HIP_TRY(launch_finalize(h->p.batch, h->L.ntiles, nslots, h->partials(), h->dq * h->dp, h->phase, resp,
+  HIP_TRY(launch_finalize(h->p.batch, h->ntiles(), nslots, h->partials(), h->dq * h->dp, h->phase, resp,
                           resp_stride, offset, h->flag(), h->stream));
   return QHFPE_OK;
 }
@@ -371,6 +377,7 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->ns = params->n_states;
   h->nc = h->ns * h->ns;
   h->levels = params->depth + 1;
+  h->cpt = cpt_default((int)L.elem, params->n_states);
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
   // setup tables, computed in FP64 and rounded once to the state precision
@@ -436,6 +443,57 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
                          h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return QHFPE_OK;
+}
+
+int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
+  if (int rc = check_handle(h)) return rc;
+  const int c = cells_per_thread == 0 ? cpt_default((int)h->L.elem, h->ns) : cells_per_thread;
+  if (!cpt_supported((int)h->L.elem, h->ns, c))
+    return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
+  h->cpt = c;
+  return QHFPE_OK;
+}
+
+int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
+  if (int rc = check_handle(h)) return rc;
+  if (reps < 1) return fail(QHFPE_EINVAL, "reps must be >= 1");
+  // time stage launches that read the state and write the scratch buffer
+  // (the state is not modified), for every available tile variant
+  const int candidates[] = {2, 4};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(QHFPE_EHIP, "hipEventCreate failed");
+  }
+  int best = h->cpt;
+  float best_ms = 1e30f;
+  int rc = QHFPE_OK;
+  for (int c : candidates) {
+    if (!cpt_supported((int)h->L.elem, h->ns, c)) continue;
+    h->cpt = c;
+    StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
+    hipError_t e = h->launch(a);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = h->launch(a);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(QHFPE_EHIP, "autotune: %s", hipGetErrorString(e));
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  h->cpt = best;
+  if (rc == QHFPE_OK && h_chosen) *h_chosen = best;
+  return rc;
 }
 
 int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase) {

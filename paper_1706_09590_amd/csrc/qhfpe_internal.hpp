@@ -31,10 +31,16 @@ inline const Plan* find_plan(int np) {
 
 // Stage workgroup shape: G = max(1, 256/np) groups of np threads; each
 // thread owns one p node of CPT consecutive q columns; a tile is TQ = G*CPT
-// columns (even, so three-state tiles can pair columns).
+// columns (even, so three-state tiles can pair columns).  CPT is a tuning
+// variant: 2 or 4 (only 2 for FP64 three-state, whose LDS tile would not
+// fit otherwise).
 constexpr int plan_groups(int np) { return np >= 256 ? 1 : 256 / np; }
-constexpr int plan_cpt(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
-constexpr int plan_tq(int np, int elem_bytes, int ns) { return plan_groups(np) * plan_cpt(elem_bytes, ns); }
+constexpr int kMinCpt = 2;
+inline bool cpt_supported(int elem_bytes, int ns, int cpt) {
+  if (elem_bytes == 8 && ns == 3) return cpt == 2;
+  return cpt == 2 || cpt == 4;
+}
+inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
 
 // Arguments of the fused RK-stage kernel (passed by value).
 struct StageArgs {
@@ -64,10 +70,10 @@ struct StageArgs {
 };
 
 // Host launchers (one translation unit per precision and state count).
-hipError_t launch_stage_f64_ns2(int np, const StageArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_stage_f64_ns3(int np, const StageArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_stage_f32_ns2(int np, const StageArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_stage_f32_ns3(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f64_ns2(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f64_ns3(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f32_ns2(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_f32_ns3(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
 
 // Pointwise and reduction kernels (aux_kernels.hip).
 struct DipoleMu {

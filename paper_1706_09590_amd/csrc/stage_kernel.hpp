@@ -48,13 +48,13 @@ QHFPE_SPLIT(192, 16, 12)
 QHFPE_SPLIT(256, 16, 16)
 #undef QHFPE_SPLIT
 
-// Launch shape of the stage kernel (see plan_tq): NT = np * G threads.
-template <typename T, int NS, int NP>
+// Launch shape of the stage kernel: NT = np * G threads, TQ = G * CPT columns.
+template <typename T, int NS, int NP, int CPT_>
 struct PlanOf {
   static constexpr int N1 = FftSplit<NP>::N1, N2 = FftSplit<NP>::N2;
   static constexpr int G = plan_groups(NP);
   static constexpr int NT = NP * G;
-  static constexpr int CPT = plan_cpt((int)sizeof(T), NS);
+  static constexpr int CPT = CPT_;
   static constexpr int TQ = G * CPT;
 };
 
@@ -71,9 +71,9 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nblocks) {
   return (bid % kXcd) * per + bid / kXcd;
 }
 
-template <typename T, int NS, int NP>
-__global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(StageArgs a) {
-  using P = PlanOf<T, NS, NP>;
+template <typename T, int NS, int NP, int CPT_>
+__global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel(StageArgs a) {
+  using P = PlanOf<T, NS, NP, CPT_>;
   constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ, NT = P::NT, CPT = P::CPT;
   constexpr int NC = NS * NS;
   constexpr int NPAIR = NS * (NS - 1) / 2;
@@ -498,13 +498,28 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP>::NT), 2) stage_kernel(Stage
   }
 }
 
+template <typename T, int NS, int NP>
+hipError_t launch_stage_np(int cpt, const StageArgs& a, int nblocks, hipStream_t s) {
+  if constexpr (sizeof(T) == 8 && NS == 3) {
+    if (cpt != 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((stage_kernel<T, NS, NP, 2>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 2>::NT), 0, s, a);
+  } else {
+    if (cpt == 2)
+      hipLaunchKernelGGL((stage_kernel<T, NS, NP, 2>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 2>::NT), 0, s, a);
+    else if (cpt == 4)
+      hipLaunchKernelGGL((stage_kernel<T, NS, NP, 4>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 4>::NT), 0, s, a);
+    else
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int NS>
-hipError_t launch_stage(int np, const StageArgs& a, int nblocks, hipStream_t s) {
+hipError_t launch_stage(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s) {
   switch (np) {
-#define QHFPE_CASE(NP_)                                                             \
-  case NP_:                                                                         \
-    hipLaunchKernelGGL((stage_kernel<T, NS, NP_>), dim3(nblocks), dim3(PlanOf<T, NS, NP_>::NT), 0, s, a); \
-    return hipGetLastError();
+#define QHFPE_CASE(NP_) \
+  case NP_:             \
+    return launch_stage_np<T, NS, NP_>(cpt, a, nblocks, s);
     QHFPE_CASE(8)
     QHFPE_CASE(12)
     QHFPE_CASE(16)

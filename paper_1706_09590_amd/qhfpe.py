@@ -70,6 +70,8 @@ def lib():
         "qhfpe_get_state": ([_vp, _vp, _c_i32], _c_int),
         "qhfpe_get_phase": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_set_member_bath": ([_vp, _c_i32, _c_dbl, _c_dbl, _c_dbl], _c_int),
+        "qhfpe_set_tile": ([_vp, _c_i32], _c_int),
+        "qhfpe_autotune": ([_vp, _c_i32, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
         "qhfpe_apply_dipole": ([_vp, _c_i32], _c_int),
         "qhfpe_step": ([_vp, _c_i64, _c_i32, _vp], _c_int),
@@ -195,6 +197,14 @@ class Propagator:
 
     def set_member_bath(self, member: int, zeta: float, gamma: float, beta: float):
         _check(lib().qhfpe_set_member_bath(self.handle, int(member), float(zeta), float(gamma), float(beta)))
+
+    def set_tile(self, cells_per_thread: int):
+        _check(lib().qhfpe_set_tile(self.handle, int(cells_per_thread)))
+
+    def autotune(self, reps: int = 20) -> int:
+        v = _c_i32(0)
+        _check(lib().qhfpe_autotune(self.handle, int(reps), ctypes.byref(v)))
+        return int(v.value)
 
     def init_thermal(self, omega: float, noise=None):
         t = self.torch

@@ -1,0 +1,105 @@
+"""Response-function and spectroscopy protocols on top of the qhfpe C-ABI.
+
+Sec. III of Ikeda & Tanimura (2017): the hierarchy is first run long enough
+to reach the correlated thermal equilibrium; impulsive dipole excitations
+mu^x at t = 0, t1 and t1 + t2 separate propagations; the trace of mu W^(0)
+gives R1(t) (Eq. R1) and R3(t3, t2, t1) (Eq. R3), and these give the
+absorption (Eq. I1), 2D correlation (Eqs. I3, nonreph, reph) and transient
+absorption (Eq. transient-absorption) spectra.
+
+This module only sequences library calls (and marshals tensors): every
+propagation, excitation, trace and spectral sum runs in the HIP library.
+The multi-time protocol uses batch members: the t1 propagation writes its
+snapshots into the members of a second handle, whose t2 propagation writes
+into a third, so all t3 propagations run as one batch.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import qhfpe
+
+
+def equilibrate(model: dict, tol: float = 1e-10, max_steps: int = 200000, check_every: int = 200,
+                omega: float = 1.0, device=None):
+    """FP64 real-time relaxation of the full hierarchy from the harmonic
+    thermal Wigner function (frequency omega) until ||L W|| / ||W|| < tol.
+    Returns (W_eq canonical complex128 [1][N+1][ns][ns][nq][np], steps, residual)."""
+    P = qhfpe.Propagator(model, batch=1, precision="fp64", device=device)
+    P.init_thermal(omega)
+    steps, res = P.relax(tol, max_steps, check_every)
+    W = P.get_state()
+    P.close()
+    return W, steps, res
+
+
+def linear_response(model: dict, nsteps: int, stride: int = 1, precision: str = "fp64", W0=None,
+                    thermal_omega: float = 1.0, noise=None, baths=None, device=None):
+    """R1(t) = (i/hbar) Tr{mu G(t) mu^x W0} sampled every stride steps.
+    baths: optional list of (zeta, gamma, beta), one batch member each.
+    Returns complex128 [B][nsteps/stride + 1]."""
+    B = 1 if baths is None else len(baths)
+    P = qhfpe.Propagator(model, batch=B, precision=precision, device=device)
+    if baths is not None:
+        for i, (z, g, b) in enumerate(baths):
+            P.set_member_bath(i, z, g, b)
+    if W0 is None:
+        P.init_thermal(thermal_omega, noise)
+    else:
+        W0 = torch.as_tensor(W0, dtype=torch.complex128, device=P.device)
+        P.set_state(W0.expand((B,) + tuple(W0.shape[1:])).contiguous() if W0.shape[0] == 1 else W0, phase=0)
+    P.apply_dipole()
+    tr = P.step(nsteps, stride)
+    P.close()
+    return (1j / model.get("hbar", 1.0)) * tr
+
+
+def third_order_response(model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, stride3: int = 1,
+                         precision: str = "fp32", device=None):
+    """R3(t3, t2, t1) = (i/hbar)^3 Tr{mu G(t3) mu^x G(t2) mu^x G(t1) mu^x W_eq}.
+
+    t1_steps, t2_steps: increasing step counts of the coherence and waiting
+    times.  W_eq: canonical complex128 [1][...] (phase 0).  Returns complex128
+    [len(t2_steps)][len(t1_steps)][n3_steps/stride3 + 1]."""
+    n1, n2 = len(t1_steps), len(t2_steps)
+    W_eq = torch.as_tensor(W_eq, dtype=torch.complex128)
+    A = qhfpe.Propagator(model, batch=1, precision=precision, device=device)
+    A.set_state(W_eq.to(A.device), phase=0)
+    A.apply_dipole()
+    B1 = qhfpe.Propagator(model, batch=n1, precision=precision, device=device)
+    done = 0
+    for i, s in enumerate(t1_steps):
+        A.step(s - done, 1, record=False)
+        done = s
+        B1.copy_members_from(A, 0, i, 1)
+    A.close()
+    B1.apply_dipole()
+    C = qhfpe.Propagator(model, batch=n1 * n2, precision=precision, device=device)
+    done = 0
+    for j, s in enumerate(t2_steps):
+        B1.step(s - done, 1, record=False)
+        done = s
+        C.copy_members_from(B1, 0, j * n1, n1)
+    B1.close()
+    C.apply_dipole()
+    tr = C.step(n3_steps, stride3)
+    C.close()
+    hb = model.get("hbar", 1.0)
+    return ((1j / hb) ** 3 * tr).reshape(n2, n1, -1)
+
+
+def absorption_spectrum(R1, dt: float, omega):
+    """I(w) = w Im int_0^inf dt e^{i w t} R1(t) (trapezoid, no window); R1 [n]."""
+    return qhfpe.spectrum_abs(R1, dt, omega)
+
+
+def correlation_spectra(R3, dt1: float, dt3: float, omega1, omega3):
+    """I_corr(w3, t2, w1) = I_NR + I_R for every waiting time: [n2][len(w3)][len(w1)]."""
+    return torch.stack([qhfpe.spectrum_corr(R3[j], dt1, dt3, omega1, omega3) for j in range(R3.shape[0])])
+
+
+def transient_absorption(R3, dt3: float, omega):
+    """I_tas(w, T) = w Im int dt e^{i w t} R3(t, T, 0) for every waiting time T
+    (the t1 = 0 slice, first coherence-time sample): [n2][len(w)]."""
+    return torch.stack([qhfpe.spectrum_abs(R3[j, 0], dt3, omega) for j in range(R3.shape[0])])

@@ -236,3 +236,24 @@ def test_member_bath_sweep_matches_separate_runs():
         m = oracle_model(di)
         _, ref = O.propagate(m, O.dipole_commutator(m, O.thermal_initial_state(m, 1.0)), 30, 3)
         assert rel(r[i], ref) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tile_variants_agree(precision):
+    """Every tile variant gives the same state and traces to rounding."""
+    d = small_model(nq=37, np_=64, depth=3)
+    out = {}
+    for cpt in (2, 4):
+        P = qhfpe.Propagator(d, batch=2, precision=precision)
+        P.set_member_bath(1, 1.0, 0.8, 0.7)
+        P.set_tile(cpt)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        out[cpt] = (P.step(12, 3).cpu().numpy(), P.get_state().cpu().numpy())
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    assert rel(out[2][1], out[4][1]) < tol
+    assert rel(out[2][0], out[4][0]) < tol
+    P = qhfpe.Propagator(d, batch=1, precision=precision)
+    assert P.autotune(3) in (2, 4)
+    with pytest.raises(qhfpe.QHFPEError):
+        P.set_tile(3)
