@@ -459,7 +459,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   if (reps < 1) return fail(QHFPE_EINVAL, "reps must be >= 1");
   // time stage launches that read the state and write the scratch buffer
   // (the state is not modified), for every available tile variant
-  const int candidates[] = {2, 4};
+  const int candidates[] = {2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -32,14 +32,15 @@ inline const Plan* find_plan(int np) {
 // Stage workgroup shape: G = max(1, 256/np) groups of np threads; each
 // thread owns one p node of CPT consecutive q columns; a tile is TQ = G*CPT
 // columns (even, so three-state tiles can pair columns).  CPT is a tuning
-// variant: 2 or 4 (only 2 for FP64 three-state, whose LDS tile would not
-// fit otherwise).
+// variant: 2, 4 or 8 for FP32 two-state; 2 or 4 for FP64 two-state and FP32
+// three-state; 2 for FP64 three-state (larger LDS tiles would not fit).
 constexpr int plan_groups(int np) { return np >= 256 ? 1 : 256 / np; }
 constexpr int kMinCpt = 2;
-inline bool cpt_supported(int elem_bytes, int ns, int cpt) {
-  if (elem_bytes == 8 && ns == 3) return cpt == 2;
-  return cpt == 2 || cpt == 4;
+constexpr bool cpt_supported_c(int elem_bytes, int ns, int cpt) {
+  return (ns == 2) ? (cpt == 2 || cpt == 4 || (cpt == 8 && elem_bytes == 4))
+                   : (elem_bytes == 8 ? cpt == 2 : (cpt == 2 || cpt == 4));
 }
+inline bool cpt_supported(int elem_bytes, int ns, int cpt) { return cpt_supported_c(elem_bytes, ns, cpt); }
 inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
 
 // Arguments of the fused RK-stage kernel (passed by value).

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   constexpr int LDP0 = NP + NP / N2;
   constexpr int LDP = (NP >= 64) ? LDP0 + ((4 - LDP0 % 16) + 16) % 16 : LDP0;
   __shared__ T sv[TQ * NC * LDP];   // v^(n) tile, then the potential term in place
-  __shared__ T sg[TQ * NC * LDP];   // field differentiated once along p, then y + coef * local terms
+  __shared__ T sg[TQ * NC * LDP];   // field differentiated once along p, then the potential term
   __shared__ cx<T> stw[N1 * (N2 + 1)];  // w^(n2 k1), row k1 padded to N2 + 1
   __shared__ T ssym[2 * NP];            // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
 
@@ -152,6 +152,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   // clamped to the grid; tiles that touch the q edges mask the ghost
   // columns to zero (a uniform branch)
   T acc[CPT][NC];
+  T hv[CPT][NC];  // v^(n) at this thread's cells (for the pointwise coupling)
   unsigned qo[CPT + 6];
   bool qin[CPT + 6];
   const bool edge = (q0 - 3 < 0) || (q0 + TQ + 3 > nq);
@@ -196,32 +197,13 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
         f += ng * zeta * p * dn[i];
       }
       acc[i][comp] = f;
+      hv[i][comp] = w0;
       sv[((cb + i) * NC + comp) * LDP + iap] = w0;
       sg[((cb + i) * NC + comp) * LDP + iap] = (!edge || qin[i + 3]) ? g : T(0);
     }
   }
-  // materialise the local terms here: otherwise their arithmetic is sunk to
-  // the parking step and every loaded q-window stays live across the barriers
-#pragma unroll
-  for (int i = 0; i < CPT; ++i)
-#pragma unroll
-    for (int comp = 0; comp < NC; ++comp) asm volatile("" : "+v"(acc[i][comp]));
-  __syncthreads();
-
-  // ---- P2: D_p of the level-coupling field and the coupling commutator ----
-  // (the periodic p-stencils acting on v^(n) itself, c_delta D_p2 and the
-  // terminator's c0 D_p D_p, are applied in the DFT domain in P5).  The RK
-  // base state y is fetched first so that its latency overlaps this phase.
-  T yv[CPT][NC];
-#pragma unroll
-  for (int i = 0; i < CPT; ++i)
-#pragma unroll
-    for (int comp = 0; comp < NC; ++comp) yv[i][comp] = buf_load<T>(ry, qo[i + 3], comp * cbytes);
+  // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p
   {
-    const T dpinv = T(1.0 / (12.0 * a.dp));
-    auto pd = [](int x) { return x + x / N2; };
-    const int am1 = pd((ia + NP - 1) % NP), am2 = pd((ia + NP - 2) % NP);
-    const int ap1 = pd((ia + 1) % NP), ap2 = pd((ia + 2) % NP);
     T coup[NS][NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
@@ -229,32 +211,55 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
       for (int k = 0; k < NS; ++k) coup[j][k] = T(a.coup[j][k]);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-      T hv[NC];
-#pragma unroll
-      for (int comp = 0; comp < NC; ++comp) {
-        const T* gg = sg + ((cb + i) * NC + comp) * LDP;
-        hv[comp] = sv[((cb + i) * NC + comp) * LDP + iap];
-        acc[i][comp] += dpinv * (-gg[ap2] + T(8) * gg[ap1] - T(8) * gg[am1] + gg[am2]);
-      }
-      // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p
       T cm[NC];
-      commutator_mi<NS, T>(coup, hv, cm);
+      commutator_mi<NS, T>(coup, hv[i], cm);
 #pragma unroll
       for (int comp = 0; comp < NC; ++comp) acc[i][comp] += cm[comp];
     }
   }
+  // materialise the local terms here: otherwise their arithmetic is sunk to
+  // the final combine and every loaded q-window stays live across the barriers
+#pragma unroll
+  for (int i = 0; i < CPT; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) asm volatile("" : "+v"(acc[i][comp]));
   __syncthreads();
+
+  // ---- P2: D_p of the level-coupling field -------------------------------
+  // (the periodic p-stencils acting on v^(n) itself, c_delta D_p2 and the
+  // terminator's c0 D_p D_p, are applied in the DFT domain in P5).  The RK
+  // base state y is fetched first so that its latency overlaps this phase;
+  // base = y + coef * (local terms) stays in registers until the combine.
+  // P2 reads only sg and the first FFT pass (P3) only sv, so the two share
+  // one phase.
+  T base[CPT][NC];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) base[i][comp] = buf_load<T>(ry, qo[i + 3], comp * cbytes);
   {
-    // park y + coef * (local terms) in sg, which P2 no longer needs
+    const T dpinv = T(1.0 / (12.0 * a.dp));
     const T coef = T(a.coef);
+    auto pd = [](int x) { return x + x / N2; };
+    const int am1 = pd((ia + NP - 1) % NP), am2 = pd((ia + NP - 2) % NP);
+    const int ap1 = pd((ia + 1) % NP), ap2 = pd((ia + 2) % NP);
 #pragma unroll
     for (int i = 0; i < CPT; ++i)
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp)
-        sg[((cb + i) * NC + comp) * LDP + iap] = yv[i][comp] + coef * acc[i][comp];
+      for (int comp = 0; comp < NC; ++comp) {
+        const T* gg = sg + ((cb + i) * NC + comp) * LDP;
+        const T f = acc[i][comp] + dpinv * (-gg[ap2] + T(8) * gg[ap1] - T(8) * gg[am1] + gg[am2]);
+        base[i][comp] += coef * f;
+      }
   }
+  // materialise base now, so the stencil operands are not kept live through
+  // the transforms
+#pragma unroll
+  for (int i = 0; i < CPT; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) asm volatile("" : "+v"(base[i][comp]));
 
-  // ---- P3..P6: potential term, in place in LDS ---------------------------
+  // ---- P3..P6: potential term (in place in sv, then sg) -------------------
   // Transform f takes its real part from one packed component column and its
   // imaginary part from another.
   auto fft_desc = [&](int f, int& colA, int& compA, int& colB, int& compB, int& kind, int& sj, int& sk) {
@@ -375,7 +380,6 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   // P5: r-space multiplication (position k2 + (N2+1) k1 holds index
   // m = k1 + N1 k2), then the first inverse pass over k2 and its twiddle;
   // results stay in registers until every thread has read its partner values.
-  cx<T> gbuf[IPT5][N2];
   const T c0t = has_up ? T(0) : c0;  // terminator level carries c0 D_p D_p
 #pragma unroll
   for (int t = 0; t < IPT5; ++t) {
@@ -413,29 +417,21 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
       }
     }
     SmallDft<N2, -1, T>::run(y);
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) gbuf[t][n2] = cmulc(y[n2], stw[k1 * (N2 + 1) + n2]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < IPT5; ++t) {
-    const int it = tid + t * NT;
-    if (it >= ITEMS5) continue;
-    const int f = it / N1, k1 = it % N1;
-    int colA, compA, colB, compB, kind, sj, sk;
-    fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * LDP + (N2 + 1) * k1;
-    T* im = sv + (colB * NC + compB) * LDP + (N2 + 1) * k1;
+    // the result goes to the same positions of sg (sv still holds partner
+    // values other threads are reading)
+    T* ore = sg + (colA * NC + compA) * LDP + (N2 + 1) * k1;
+    T* oim = sg + (colB * NC + compB) * LDP + (N2 + 1) * k1;
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) {
-      re[n2] = gbuf[t][n2].re;
-      im[n2] = gbuf[t][n2].im;
+      const cx<T> g = cmulc(y[n2], stw[k1 * (N2 + 1) + n2]);
+      ore[n2] = g.re;
+      oim[n2] = g.im;
     }
   }
   __syncthreads();
 
   // P6: second inverse pass, item (f, n2): N1-point DFTs over stride N2,
-  // natural order out.
+  // natural order out (in place in sg).
 #pragma unroll
   for (int t = 0; t < (ITEMS3 + NT - 1) / NT; ++t) {
     const int it = tid + t * NT;
@@ -443,8 +439,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const int f = it / N2, n2 = it % N2;
     int colA, compA, colB, compB, kind, sj, sk;
     fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
-    T* re = sv + (colA * NC + compA) * LDP;
-    T* im = sv + (colB * NC + compB) * LDP;
+    T* re = sg + (colA * NC + compA) * LDP;
+    T* im = sg + (colB * NC + compB) * LDP;
     cx<T> x[N1];
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) x[k1] = {re[n2 + (N2 + 1) * k1], im[n2 + (N2 + 1) * k1]};
@@ -470,8 +466,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     T o[NC];
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
-      const int li = ((cb + i) * NC + comp) * LDP + iap;
-      o[comp] = sg[li] + coef * sv[li];
+      o[comp] = base[i][comp] + coef * sg[((cb + i) * NC + comp) * LDP + iap];
       buf_store(o[comp], ro, qo[i + 3], comp * cbytes);
     }
     if (want_trace) {
@@ -498,20 +493,28 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   }
 }
 
+template <typename T, int NS, int NP, int CPT>
+hipError_t launch_stage_variant(const StageArgs& a, int nblocks, hipStream_t s) {
+  if constexpr (cpt_supported_c((int)sizeof(T), NS, CPT)) {
+    hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int NS, int NP>
 hipError_t launch_stage_np(int cpt, const StageArgs& a, int nblocks, hipStream_t s) {
-  if constexpr (sizeof(T) == 8 && NS == 3) {
-    if (cpt != 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage_kernel<T, NS, NP, 2>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 2>::NT), 0, s, a);
-  } else {
-    if (cpt == 2)
-      hipLaunchKernelGGL((stage_kernel<T, NS, NP, 2>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 2>::NT), 0, s, a);
-    else if (cpt == 4)
-      hipLaunchKernelGGL((stage_kernel<T, NS, NP, 4>), dim3(nblocks), dim3(PlanOf<T, NS, NP, 4>::NT), 0, s, a);
-    else
+  switch (cpt) {
+    case 2:
+      return launch_stage_variant<T, NS, NP, 2>(a, nblocks, s);
+    case 4:
+      return launch_stage_variant<T, NS, NP, 4>(a, nblocks, s);
+    case 8:
+      return launch_stage_variant<T, NS, NP, 8>(a, nblocks, s);
+    default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T, int NS>
