@@ -53,7 +53,7 @@ def read_traffic(precision: str):
         return None
 
 
-def cpu_baseline(model: dict, nsteps: int = 4):
+def cpu_baseline(model: dict, nsteps: int = 30):
     """The FP64 oracle, single-threaded, on a bounded sample: `nsteps` RK4
     steps of the same 256 x 256 depth-8 hierarchy (zeta = 1.0)."""
     for v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--nsteps", type=int, default=20000, help="RK4 steps per propagation")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="cells per thread of the stage kernel (0: autotune before the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
@@ -134,6 +136,13 @@ def main():
         P = qhfpe.Propagator(base, batch=len(zetas), precision=precision, device=dev, stream=stream)
         for i, z in enumerate(zetas):
             P.set_member_bath(i, z, base["gamma"], base["beta"])
+        # pick the tile variant on this device before the timed region
+        P.init_thermal(1.0)
+        if args.tile:
+            P.set_tile(args.tile)
+            tile = args.tile
+        else:
+            tile = P.autotune(20)
         resp = torch.empty((len(zetas), nsteps + 1), dtype=torch.complex128, device=dev)
         spec = [None] * len(zetas)
 
@@ -172,6 +181,7 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
                     avg_launch_us=round(launch_s * 1e6, 3), bytes_per_launch=bytes_per_launch,
+                    cells_per_thread=tile,
                     kernel_source_sha=kernel_source_sha())
         out = dict(value=updates / wall, wall_s=wall, gpu_s=gpu_s, ms_per_step=1e3 * wall / steps,
                    roofline=roof, resp=resp.cpu().numpy(), spec=[s.cpu().numpy() for s in spec])

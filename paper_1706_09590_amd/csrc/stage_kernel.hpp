@@ -62,9 +62,9 @@ struct PlanOf {
 // is the mirror image with opposite sign (Sec. III).
 __device__ constexpr double kUpwind[6] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0};
 
-// Fixed-slot block order: a tile's q neighbours and its hierarchy
-// neighbours are placed on the same XCD (blocks are dealt round-robin over
-// the 8 XCDs), so halo and level reads hit that XCD's L2.
+// Hardware block ids are dealt round-robin over the 8 XCDs; this maps them
+// so that each XCD receives one contiguous range of logical blocks (whole
+// q tiles with all their levels), so halo and level reads hit that XCD's L2.
 __device__ __forceinline__ int xcd_logical_block(int bid, int nblocks) {
   constexpr int kXcd = 8;
   const int per = (nblocks + kXcd - 1) / kXcd;
@@ -98,11 +98,14 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   const int lb = xcd_logical_block(blockIdx.x, a.nblocks_padded);
   if (lb >= nblocks) return;
   const int tid = threadIdx.x;
-  const int tile = lb % a.ntiles;
-  const int rest = lb / a.ntiles;
+  // levels run fastest: the blocks of every level of one q tile are
+  // resident together, so the reads of v^(n) by levels n - 1 and n + 1
+  // hit the copy that level n's own block brought into L2
   const int L = a.depth + 1;
-  const int n = rest % L;
-  const int b = rest / L;
+  const int n = lb % L;
+  const int rest = lb / L;
+  const int tile = rest % a.ntiles;
+  const int b = rest / a.ntiles;
   const int q0 = tile * TQ;
   const int nq = a.nq;
   const int ia = tid % NP;           // this thread's p node
