@@ -58,6 +58,13 @@ struct PlanOf {
   static constexpr int TQ = G * CPT;
 };
 
+// One complex transform of a tile: real part from (colA, compA), imaginary
+// part from (colB, compB); kind 0 packs two real diagonal components of
+// states sj and sk, kind 1 is the off-diagonal pair (sj, sk).
+struct FftItem {
+  int colA, compA, colB, compB, kind, sj, sk;
+};
+
 // Upwind coefficients (x60) for p >= 0 on offsets -3..2; the p < 0 stencil
 // is the mirror image with opposite sign (Sec. III).
 __device__ constexpr double kUpwind[6] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0};
@@ -166,8 +173,10 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     qo[j] = ((unsigned)(q < 0 ? 0 : (q >= nq ? nq - 1 : q)) * NP + ia) * ES;
   }
   // components are processed in groups of LGRP; the scheduling barrier keeps
-  // the next group's loads from being hoisted, which bounds register use
-  constexpr int LGRP = (sizeof(T) == 8) ? 1 : 2;
+  // the next group's loads from being hoisted, which bounds register use.
+  // FP64 tiles are held to two workgroups per CU by LDS, which leaves room
+  // for all loads at once; FP32 runs four workgroups and loads in halves.
+  constexpr int LGRP = (sizeof(T) == 8) ? NC : 2;
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     if (comp % LGRP == 0 && comp > 0) __builtin_amdgcn_sched_barrier(0);
@@ -226,20 +235,21 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   for (int i = 0; i < CPT; ++i)
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) asm volatile("" : "+v"(acc[i][comp]));
-  __syncthreads();
-
-  // ---- P2: D_p of the level-coupling field -------------------------------
-  // (the periodic p-stencils acting on v^(n) itself, c_delta D_p2 and the
-  // terminator's c0 D_p D_p, are applied in the DFT domain in P5).  The RK
-  // base state y is fetched first so that its latency overlaps this phase;
-  // base = y + coef * (local terms) stays in registers until the combine.
-  // P2 reads only sg and the first FFT pass (P3) only sv, so the two share
-  // one phase.
+  // the RK base state y is fetched now, so that its latency overlaps the
+  // barrier and the stencil of P2
   T base[CPT][NC];
 #pragma unroll
   for (int i = 0; i < CPT; ++i)
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) base[i][comp] = buf_load<T>(ry, qo[i + 3], comp * cbytes);
+  __syncthreads();
+
+  // ---- P2: D_p of the level-coupling field -------------------------------
+  // (the periodic p-stencils acting on v^(n) itself, c_delta D_p2 and the
+  // terminator's c0 D_p D_p, are applied in the DFT domain in P5).
+  // base = y + coef * (local terms) stays in registers until the combine.
+  // P2 reads only sg and the first FFT pass (P3) only sv, so the two share
+  // one phase.
   {
     const T dpinv = T(1.0 / (12.0 * a.dp));
     const T coef = T(a.coef);
@@ -265,38 +275,36 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   // ---- P3..P6: potential term (in place in sv, then sg) -------------------
   // Transform f takes its real part from one packed component column and its
   // imaginary part from another.
-  auto fft_desc = [&](int f, int& colA, int& compA, int& colB, int& compB, int& kind, int& sj, int& sk) {
-    // kind 0: two real diagonal components (state sj of colA, sk of colB)
-    // kind 1: off-diagonal pair (sj, sk) of column colA
-    if (f < TQ) {
-      colA = colB = f;
-      compA = 0;
-      compB = 1;
-      kind = 0;
-      sj = 0;
-      sk = 1;
-      return;
+  // (returned by value: out-parameters here were demoted to scratch memory)
+  auto fft_desc = [](int f) {
+    FftItem d;
+    if (f < TQ) {  // diagonal pair (0, 1) of column f
+      d.colA = d.colB = f;
+      d.compA = 0;
+      d.compB = 1;
+      d.kind = 0;
+      d.sj = 0;
+      d.sk = 1;
+      return d;
     }
     f -= TQ;
-    if (NS == 3 && f < TQ / 2) {
-      colA = 2 * f;
-      colB = 2 * f + 1;
-      compA = compB = 2;
-      kind = 0;
-      sj = sk = 2;
-      return;
+    if (NS == 3 && f < TQ / 2) {  // diagonal 2 of columns 2f and 2f + 1
+      d.colA = 2 * f;
+      d.colB = 2 * f + 1;
+      d.compA = d.compB = 2;
+      d.kind = 0;
+      d.sj = d.sk = 2;
+      return d;
     }
     if (NS == 3) f -= TQ / 2;
-    const int c = f / NPAIR;
-    const int pr = f % NPAIR;
-    const int j = (pr < NS - 1) ? 0 : 1;
-    const int k = (pr == 0) ? 1 : 2;
-    colA = colB = c;
-    sj = j;
-    sk = k;
-    compA = Packing<NS>::re(j, k);
-    compB = compA + 1;
-    kind = 1;
+    const int pr = f % NPAIR;  // off-diagonal pair (j, k) of column f / NPAIR
+    d.colA = d.colB = f / NPAIR;
+    d.sj = (pr < NS - 1) ? 0 : 1;
+    d.sk = (pr == 0) ? 1 : 2;
+    d.compA = NS + 2 * pr;
+    d.compB = d.compA + 1;
+    d.kind = 1;
+    return d;
   };
 
   // P3: first forward pass, item (f, n2): N1-point DFTs over stride N2.
@@ -306,8 +314,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const int it = tid + t * NT;
     if (it >= ITEMS3) continue;
     const int f = it / N2, n2 = it % N2;
-    int colA, compA, colB, compB, kind, sj, sk;
-    fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+    const FftItem d = fft_desc(f);
+    const int colA = d.colA, compA = d.compA, colB = d.colB, compB = d.compB, kind = d.kind;
     T* re = sv + (colA * NC + compA) * LDP;
     T* im = sv + (colB * NC + compB) * LDP;
     cx<T> x[N1];
@@ -337,8 +345,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     for (int t = 0; t < IPT5; ++t) {
       const int it = tid + t * NT;
       const int f = (it < ITEMS5 ? it : 0) / N1, k1 = it % N1;
-      int colA, compA, colB, compB, kind, sj, sk;
-      fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+      const FftItem d = fft_desc(f);
+      const int colA = d.colA, colB = d.colB, kind = d.kind, sj = d.sj, sk = d.sk;
       const int qa = min(q0 + colA, nq - 1), qb = min(q0 + colB, nq - 1);
       const unsigned oa = ((unsigned)qa * NP + k1) * ES, ob = ((unsigned)qb * NP + k1) * ES;
 #pragma unroll
@@ -358,8 +366,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const int it = tid + t * NT;
     if (it >= ITEMS5) continue;
     const int f = it / N1, k1 = it % N1;
-    int colA, compA, colB, compB, kind, sj, sk;
-    fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+    const FftItem d = fft_desc(f);
+    const int colA = d.colA, compA = d.compA, colB = d.colB, compB = d.compB, kind = d.kind;
     T* re = sv + (colA * NC + compA) * LDP + (N2 + 1) * k1;
     T* im = sv + (colB * NC + compB) * LDP + (N2 + 1) * k1;
     cx<T> x[N2];
@@ -389,8 +397,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const int it = tid + t * NT;
     if (it >= ITEMS5) continue;
     const int f = it / N1, k1 = it % N1;
-    int colA, compA, colB, compB, kind, sj, sk;
-    fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+    const FftItem d = fft_desc(f);
+    const int colA = d.colA, compA = d.compA, colB = d.colB, compB = d.compB, kind = d.kind;
     const T* re = sv + (colA * NC + compA) * LDP;
     const T* im = sv + (colB * NC + compB) * LDP;
     const T* zr = re + (N2 + 1) * k1;
@@ -440,8 +448,8 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const int it = tid + t * NT;
     if (it >= ITEMS3) continue;
     const int f = it / N2, n2 = it % N2;
-    int colA, compA, colB, compB, kind, sj, sk;
-    fft_desc(f, colA, compA, colB, compB, kind, sj, sk);
+    const FftItem d = fft_desc(f);
+    const int colA = d.colA, compA = d.compA, colB = d.colB, compB = d.compB, kind = d.kind;
     T* re = sg + (colA * NC + compA) * LDP;
     T* im = sg + (colB * NC + compB) * LDP;
     cx<T> x[N1];
