@@ -112,14 +112,15 @@ int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
  * applies.  Synchronous. */
 int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta);
 
-/* Tile variant of the fused RK stage: each thread of a stage workgroup owns
- * cells_per_thread consecutive q columns (2, 4 or 8 for FP32 two-state; 2 or
- * 4 for FP64 two-state and FP32 three-state; 2 for FP64 three-state;
- * 0 = default).  Variants
- * compute the same operations per cell; results agree to rounding (the
- * compiled instruction order and the grouping of the trace partial sums
- * differ).  QHFPE_EUNSUPPORTED if the variant does not exist for this
- * precision and state count. */
+/* Tile variant of the fused RK stage.  2, 4, 8: each thread of a stage
+ * workgroup owns cells_per_thread consecutive q columns (2, 4 or 8 for FP32
+ * two-state; 2 or 4 for FP64 two-state and FP32 three-state; 2 for FP64
+ * three-state).  1: the wave-independent variant, one 64-lane wave per pair
+ * of q columns, each lane holding np/64 consecutive p nodes (two states and
+ * np = 256 only).  0 = default.  Variants compute the same operations per
+ * cell; results agree to rounding (the compiled instruction order and the
+ * grouping of the trace partial sums differ).  QHFPE_EUNSUPPORTED if the
+ * variant does not exist for this precision, state count and np. */
 int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread);
 
 /* Pick the fastest tile variant for this handle by timing reps stage launches

@@ -200,6 +200,92 @@ __device__ __forceinline__ void buf_store(double v, rsrc_t r, unsigned voff, uns
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
 }
 
+// Four consecutive elements per lane (one 16-byte access for float, two for
+// double); voff must be 16-byte aligned.  The loaded vector is bit-cast as a
+// whole: taking single 32-bit elements out of it and bit-casting those makes
+// this compiler shrink the load to one dword at offset 0 (every element
+// then reads element 0).
+typedef float qhfpe_f2 __attribute__((ext_vector_type(2)));
+typedef float qhfpe_f4 __attribute__((ext_vector_type(4)));
+typedef double qhfpe_d2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Quad {
+  T v[4];
+};
+__device__ __forceinline__ Quad<float> buf_load4(rsrc_t r, unsigned voff, unsigned soff, float) {
+  const qhfpe_f4 x = __builtin_bit_cast(qhfpe_f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  return {{x[0], x[1], x[2], x[3]}};
+}
+__device__ __forceinline__ Quad<double> buf_load4(rsrc_t r, unsigned voff, unsigned soff, double) {
+  const qhfpe_d2 x = __builtin_bit_cast(qhfpe_d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  const qhfpe_d2 y =
+      __builtin_bit_cast(qhfpe_d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff + 16, (int)soff, 0));
+  return {{x[0], x[1], y[0], y[1]}};
+}
+__device__ __forceinline__ void buf_store4(const Quad<float>& q, rsrc_t r, unsigned voff, unsigned soff) {
+  using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  const qhfpe_f4 x = {q.v[0], q.v[1], q.v[2], q.v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store4(const Quad<double>& q, rsrc_t r, unsigned voff, unsigned soff) {
+  using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  const qhfpe_d2 x = {q.v[0], q.v[1]}, y = {q.v[2], q.v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, y), r, (int)voff + 16, (int)soff, 0);
+}
+
+// M consecutive elements per lane (M * sizeof(T) = 8, 16 or 32 bytes; voff
+// aligned to that size, at most 16).
+template <int M>
+__device__ __forceinline__ void buf_load_n(rsrc_t r, unsigned voff, unsigned soff, float* out) {
+  static_assert(M == 2 || M == 4, "2 or 4 floats");
+  if constexpr (M == 2) {
+    const qhfpe_f2 x = __builtin_bit_cast(qhfpe_f2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    out[0] = x[0];
+    out[1] = x[1];
+  } else {
+    const Quad<float> q = buf_load4(r, voff, soff, 0.0f);
+    for (int j = 0; j < 4; ++j) out[j] = q.v[j];
+  }
+}
+template <int M>
+__device__ __forceinline__ void buf_load_n(rsrc_t r, unsigned voff, unsigned soff, double* out) {
+  static_assert(M == 2 || M == 4, "2 or 4 doubles");
+  if constexpr (M == 2) {
+    const qhfpe_d2 x = __builtin_bit_cast(qhfpe_d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    out[0] = x[0];
+    out[1] = x[1];
+  } else {
+    const Quad<double> q = buf_load4(r, voff, soff, 0.0);
+    for (int j = 0; j < 4; ++j) out[j] = q.v[j];
+  }
+}
+
+// Cross-lane rotations over the whole 64-lane wave (DPP wave_ror:1 /
+// wave_rol:1): lane_prev returns lane l-1's value (lane 0 gets lane 63's),
+// lane_next lane l+1's (lane 63 gets lane 0's).
+__device__ __forceinline__ int dpp_prev(int x) { return __builtin_amdgcn_mov_dpp(x, 0x13C, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_next(int x) { return __builtin_amdgcn_mov_dpp(x, 0x134, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_prev(float x) { return __builtin_bit_cast(float, dpp_prev(__builtin_bit_cast(int, x))); }
+__device__ __forceinline__ float lane_next(float x) { return __builtin_bit_cast(float, dpp_next(__builtin_bit_cast(int, x))); }
+__device__ __forceinline__ double lane_prev(double x) {
+  const auto v = __builtin_bit_cast(int __attribute__((ext_vector_type(2))), x);
+  return __builtin_bit_cast(double, (int __attribute__((ext_vector_type(2)))){dpp_prev(v[0]), dpp_prev(v[1])});
+}
+__device__ __forceinline__ double lane_next(double x) {
+  const auto v = __builtin_bit_cast(int __attribute__((ext_vector_type(2))), x);
+  return __builtin_bit_cast(double, (int __attribute__((ext_vector_type(2)))){dpp_next(v[0]), dpp_next(v[1])});
+}
+
+// Orders LDS accesses of one wave: accesses before it (of any lane) are
+// performed before accesses after it.  LDS executes a wave's instructions
+// in order, so only the compiler has to be kept from moving them across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // Hermitian-packed electronic matrices.  Component order: diagonal j at j;
 // off-diagonal pair (j, k), j < k, at NS + 2 * pair(j, k) (re) and +1 (im),

@@ -44,7 +44,7 @@ struct Layout {
   long long member_elems = 0, level_elems = 0, comp_elems = 0;
   size_t state_bytes = 0;
   size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
-  size_t off_dtab = 0, off_gtab = 0, off_bath = 0, off_psym = 0;
+  size_t off_dtab = 0, off_gtab = 0, off_mtab = 0, off_bath = 0, off_psym = 0;
   int n1 = 0, n2 = 0;
   size_t total = 0;
   size_t red_count = 0;
@@ -124,6 +124,8 @@ Layout make_layout(const qhfpe_params* p) {
   off += align_up((size_t)ns * L.comp_elems * L.elem);
   L.off_gtab = off;
   off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
+  L.off_mtab = off;
+  if (wave_supported(ns, p->np)) off += align_up((size_t)3 * L.comp_elems * L.elem);
   L.off_bath = off;
   off += align_up((size_t)p->batch * kBathStride * sizeof(double));
   L.off_psym = off;
@@ -187,6 +189,25 @@ void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<
   }
 }
 
+// The multiplier tables of the wave variant in one array, each q row
+// permuted so that the 16 values m = k1 + 16 k2 (k2 = 0..15) of row k1 are
+// contiguous; the coupling table is stored halved (the kernel treats it as
+// a pair of equal diagonal multipliers).
+void wave_tables(const qhfpe_params& p, const std::vector<double>& dtab, const std::vector<double>& gtab,
+                 std::vector<double>& mtab) {
+  const int nq = p.nq, np = p.np, n1 = 16, n2 = np / 16;
+  const size_t plane = (size_t)nq * np;
+  mtab.assign(3 * plane, 0.0);
+  for (int t = 0; t < 3; ++t)
+    for (int i = 0; i < nq; ++i)
+      for (int k1 = 0; k1 < n1; ++k1)
+        for (int k2 = 0; k2 < n2; ++k2) {
+          const size_t src = (size_t)i * np + k1 + n1 * k2;
+          const double v = (t < 2) ? dtab[t * plane + src] : 0.5 * gtab[src];
+          mtab[t * plane + (size_t)i * np + (size_t)k1 * n2 + k2] = v;
+        }
+}
+
 // Symbols of the periodic fourth-order p-stencils in the DFT convention
 // rho~[m] = sum_a W[a] exp(+2 pi i a m / np): a stencil sum_k c_k W[a + k]
 // multiplies rho~[m] by sum_k c_k exp(-i k theta), theta = 2 pi m / np.
@@ -230,7 +251,8 @@ struct qhfpe_handle {
   int ns = 0, nc = 0, levels = 0;
   int cpt = 4;  // stage tile variant (cells per thread along q)
 
-  int tq() const { return plan_groups(p.np) * cpt; }
+  bool wave() const { return cpt == kTileWave; }
+  int tq() const { return wave() ? 2 : plan_groups(p.np) * cpt; }
   int ntiles() const { return (p.nq + tq() - 1) / tq(); }
   double dq = 0, dp = 0;
 
@@ -242,6 +264,7 @@ struct qhfpe_handle {
   void* twiddle() const { return ws + L.off_tw; }
   void* dtab() const { return ws + L.off_dtab; }
   void* gtab() const { return ws + L.off_gtab; }
+  void* mtab() const { return ws + L.off_mtab; }
   double* bath() const { return reinterpret_cast<double*>(ws + L.off_bath); }
   void* psym() const { return ws + L.off_psym; }
   int* flag() const { return reinterpret_cast<int*>(ws + L.off_flag); }
@@ -270,6 +293,7 @@ struct qhfpe_handle {
     a.twiddle2 = twiddle();
     a.dtab = dtab();
     a.gtab = gtab();
+    a.mtab = wave_supported(ns, p.np) ? mtab() : nullptr;
     a.bath = bath();
     a.psym = psym();
     a.slot = 0;
@@ -277,7 +301,9 @@ struct qhfpe_handle {
     a.depth = p.depth;
     a.ntiles = ntiles();
     a.batch = p.batch;
-    a.nblocks_padded = (ntiles() * levels * p.batch + 7) / 8 * 8;
+    const int units = ntiles() * levels * p.batch;  // workgroups, or waves of the wave variant
+    const int blocks = wave() ? (units + kWaveTasksPerBlock - 1) / kWaveTasksPerBlock : units;
+    a.nblocks_padded = (blocks + 7) / 8 * 8;
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;
@@ -296,6 +322,8 @@ struct qhfpe_handle {
 
   hipError_t launch(const StageArgs& a) const {
     const int nblocks = a.nblocks_padded;
+    if (wave())
+      return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(a, nblocks, stream) : launch_stage_wave_f32(a, nblocks, stream);
     if (p.precision == QHFPE_FP64)
       return ns == 2 ? launch_stage_f64_ns2(p.np, cpt, a, nblocks, stream)
                      : launch_stage_f64_ns3(p.np, cpt, a, nblocks, stream);
@@ -385,6 +413,8 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   twiddle_table(params->np, L.n1, L.n2, tw);
   stencil_symbols(params->np, h->dp, sym);
   multiplier_tables(*params, h->dq, h->dp, dt, gt);
+  std::vector<double> mt;
+  if (wave_supported(params->n_states, params->np)) wave_tables(*params, dt, gt, mt);
   std::vector<double> bath((size_t)params->batch * kBathStride);
   double bc[kBathStride];
   bath_constants(*params, params->zeta, params->gamma, params->beta, bc);
@@ -404,6 +434,7 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   up(h->twiddle(), tw);
   up(h->dtab(), dt);
   up(h->gtab(), gt);
+  up(h->mtab(), mt);
   up(h->psym(), sym);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bath(), bath.data(), bath.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
@@ -448,7 +479,7 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
 int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
   if (int rc = check_handle(h)) return rc;
   const int c = cells_per_thread == 0 ? cpt_default((int)h->L.elem, h->ns) : cells_per_thread;
-  if (!cpt_supported((int)h->L.elem, h->ns, c))
+  if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c))
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
   h->cpt = c;
   return QHFPE_OK;
@@ -459,7 +490,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   if (reps < 1) return fail(QHFPE_EINVAL, "reps must be >= 1");
   // time stage launches that read the state and write the scratch buffer
   // (the state is not modified), for every available tile variant
-  const int candidates[] = {2, 4, 8};
+  const int candidates[] = {kTileWave, 2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -470,7 +501,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   float best_ms = 1e30f;
   int rc = QHFPE_OK;
   for (int c : candidates) {
-    if (!cpt_supported((int)h->L.elem, h->ns, c)) continue;
+    if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c)) continue;
     h->cpt = c;
     StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
     hipError_t e = h->launch(a);  // warm-up

@@ -1,0 +1,395 @@
+// Fused RK4 stage, wave-independent variant for two electronic states and
+// np = 256:  out = y + coef * L v  with the same operator as stage_kernel.hpp
+// (Eq. (heom) of Ikeda & Tanimura (2017) with one Drude exponential and
+// V(q) = q, closed by Eq. (GMFP); potential term of Eq.
+// (quantum-liouvillian) through the DFT along p; Sec. III discretisation).
+//
+// One wave owns a whole task: two neighbouring q columns of one level of one
+// batch member, all four packed components.  Lane l holds the p nodes
+// 4l .. 4l+3 of both columns.  The waves of a workgroup share only the
+// twiddle and symbol tables (loaded once behind the single workgroup
+// barrier); every later step orders its LDS accesses within the wave, so a
+// wave waiting for memory never stalls another.
+//
+//  - kinetic -(p/m) D_q: 5th-order upwind over an 8-column q window;
+//  - D_p of the level field g: the stencil neighbours p +- 1, +- 2 of a
+//    lane's four nodes are its own or the neighbouring lanes' (DPP wave
+//    rotations; the p grid is periodic and one column fills the wave);
+//  - potential term: four complex 256-point transforms per task (the two
+//    real diagonals of a column packed into one, the off-diagonal pair in
+//    another), 16 x 16 two-pass FFT with one radix-16 item per lane and
+//    pass, r-space multiply in place (all lanes read their own and partner
+//    rows before any lane writes), inverse transform;
+//  - constant diabatic coupling: pointwise commutator in p.
+#pragma once
+
+#include "device_common.hpp"
+#include "qhfpe_internal.hpp"
+#include "stage_kernel.hpp"
+
+namespace qhfpe {
+
+struct WavePlan {
+  static constexpr int NP = 256, N1 = 16, N2 = 16;
+  static constexpr int K = 4;    // p nodes per lane
+  static constexpr int C = 2;    // q columns per task
+  static constexpr int NC = 4;   // packed components (two states)
+  static constexpr int WPB = kWaveTasksPerBlock;  // waves per workgroup
+  static constexpr int NT = 64 * WPB;
+  static constexpr int LDP0 = NP + NP / N2;
+  static constexpr int LDP = LDP0 + ((4 - LDP0 % 16) + 16) % 16;
+};
+
+// Position of p node a in a padded LDS column (one pad element per N2 block).
+__device__ __forceinline__ constexpr int wave_pad(int a) { return a + a / WavePlan::N2; }
+
+template <typename T>
+__global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a) {
+  using W = WavePlan;
+  constexpr int NP = W::NP, N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
+  constexpr int LDP = W::LDP;
+  __shared__ T sbuf[WPB][C * NC * LDP];  // per wave: v tile, transformed in place
+  __shared__ cx<T> stw[N1 * (N2 + 1)];   // w^(n2 k1), row k1 padded to N2 + 1
+  __shared__ T ssym[2 * NP];             // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
+
+  const int tid = threadIdx.x;
+  for (int j = tid; j < N1 * (N2 + 1); j += W::NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
+  for (int j = tid; j < 2 * NP; j += W::NT) ssym[j] = static_cast<const T*>(a.psym)[j];
+  __syncthreads();  // the only workgroup barrier
+
+  // the wave index is uniform across the wave; saying so keeps every
+  // quantity derived from it (task, level, member, buffer descriptors) in
+  // scalar registers instead of per-lane loops over descriptor values
+  const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nq = a.nq;
+  const int npairs = a.ntiles;  // tasks per level = column pairs
+  const int L = a.depth + 1;
+  const int ntasks = npairs * L * a.batch;
+  // levels fastest, as in stage_kernel: the tasks of all levels of one
+  // column pair run together and share their level neighbours through L2
+  const int task = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
+  if (task >= ntasks) return;
+  const int n = task % L;
+  const int pair = (task / L) % npairs;
+  const int b = task / (L * npairs);
+  const int q0 = 2 * pair;
+  T* const s = sbuf[wid];
+
+  constexpr unsigned ES = sizeof(T);
+  const unsigned level_bytes = (unsigned)(a.level_stride * ES);
+  const unsigned cbytes = (unsigned)(a.comp_stride * ES);
+  const T* vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
+  // Loads past a descriptor's size return zero.  That supplies the zero
+  // ghost columns beyond the q edges (their offsets are set past every
+  // level), v^(n+1) at n = N, v^(n-1) at n = 0 and a missing y.
+  const bool has_up = n < a.depth, has_dn = n >= 1;
+  const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);
+  const rsrc_t ru = make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, has_up ? level_bytes : 0u);
+  const rsrc_t rd = make_rsrc(vm + (long long)(has_dn ? n - 1 : n) * a.level_stride, has_dn ? level_bytes : 0u);
+  const bool has_y = a.y != nullptr;
+  const rsrc_t ry = make_rsrc(has_y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride +
+                                          (long long)n * a.level_stride
+                                    : vm,
+                              has_y ? level_bytes : 0u);
+
+  const double* bath = a.bath + kBathStride * b;
+  const T zeta = T(bath[0]), c0 = T(bath[2]), cdel = T(bath[3]);
+  const T ng = T(n * bath[1]);
+  const T coef = T(a.coef);
+  const int a0 = K * lane;  // first p node of this lane
+  T p[K], kscale[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    p[j] = T(a.p0 + (a0 + j) * a.dp);
+    kscale[j] = -(p[j] * T(a.inv_mass)) * T(1.0 / (60.0 * a.dq));
+  }
+  // upwind coefficients (x60) on q offsets -3..3 for the sign of p at this
+  // lane's first node; nodes of the other sign (only where p = 0 falls
+  // inside a lane) are redone below
+  const bool pos0 = p[0] >= T(0);
+  T kc[7], kcm[7];  // this lane's stencil and the mirrored one
+#pragma unroll
+  for (int o = -3; o <= 3; ++o) {
+    const double cp = (o <= 2) ? kUpwind[o + 3] : 0.0;
+    const double cn = (o >= -2) ? -kUpwind[3 - o] : 0.0;
+    kc[o + 3] = T(pos0 ? cp : cn);
+    kcm[o + 3] = T(pos0 ? cn : cp);
+  }
+  const bool mixed = (p[K - 1] >= T(0)) != pos0;
+  const bool any_mixed = __any(mixed);
+
+  // byte offsets of the q columns q0-3 .. q0+4 at this lane's first node;
+  // columns outside the grid point past the end of every level (read as 0)
+  constexpr unsigned kGhost = 0x7fffff00u;
+  unsigned qo[C + 6];
+#pragma unroll
+  for (int t = 0; t < C + 6; ++t) {
+    const int q = q0 + t - 3;
+    qo[t] = (q >= 0 && q < nq) ? ((unsigned)q * NP + a0) * ES : kGhost;
+  }
+  const T dpinv = T(1.0 / (12.0 * a.dp));
+  // the terminator level differentiates zeta p v^(N) in place of v^(N+1)
+  const T zterm = has_up ? T(0) : zeta;
+
+  // ---- local terms, one component at a time ------------------------------
+  // The kinetic window is loaded in node halves for double (two nodes per
+  // 16-byte access), so that one half-window is in flight at a time.
+  constexpr int KH = (sizeof(T) == 8) ? 2 : 4;  // nodes per kinetic pass
+  T base[C][NC][K];  // y + coef * (all terms except the potential)
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    if (comp > 0) __builtin_amdgcn_sched_barrier(0);
+    const unsigned so = comp * cbytes;
+    // level field and level terms at all four nodes of both columns
+    T lev[C][K];
+    {
+      Quad<T> up[C], dn[C], wc[C];
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        wc[i] = buf_load4(rn, qo[i + 3], so, T(0));
+        up[i] = buf_load4(ru, qo[i + 3], so, T(0));
+        dn[i] = buf_load4(rd, qo[i + 3], so, T(0));
+      }
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        T g[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const T w0 = wc[i].v[j];
+          // field differentiated once along p:
+          //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
+          // (the absent neighbour levels read as zero; n gamma = 0 at n = 0)
+          g[j] = up[i].v[j] + (zterm * p[j]) * w0 + (ng * c0) * dn[i].v[j];
+          lev[i][j] = -ng * w0 + (ng * zeta * p[j]) * dn[i].v[j];
+          s[(i * NC + comp) * LDP + wave_pad(a0 + j)] = w0;
+        }
+        // D_p g: nodes a0-2, a0-1 come from the previous lane, a0+4, a0+5
+        // from the next one (periodic in p: one column spans the whole wave)
+        T e[K + 4];
+        e[0] = lane_prev(g[K - 2]);
+        e[1] = lane_prev(g[K - 1]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) e[j + 2] = g[j];
+        e[K + 2] = lane_next(g[0]);
+        e[K + 3] = lane_next(g[1]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          lev[i][j] += dpinv * (-e[j + 4] + T(8) * e[j + 3] - T(8) * e[j + 1] + e[j]);
+          // materialised here, so that its operands are not kept live
+          asm volatile("" : "+v"(lev[i][j]));
+        }
+      }
+    }
+    // kinetic term and the base state
+#pragma unroll
+    for (int h = 0; h < K / KH; ++h) {
+      if (h > 0) __builtin_amdgcn_sched_barrier(0);
+      const unsigned ho = h * KH * ES;
+      T w[C + 6][KH], yv[C][KH];
+#pragma unroll
+      for (int t = 0; t < C + 6; ++t) buf_load_n<KH>(rn, qo[t] + ho, so, w[t]);
+#pragma unroll
+      for (int i = 0; i < C; ++i) buf_load_n<KH>(ry, qo[i + 3] + ho, so, yv[i]);
+#pragma unroll
+      for (int i = 0; i < C; ++i)
+#pragma unroll
+        for (int jj = 0; jj < KH; ++jj) {
+          const int j = h * KH + jj;
+          T kin = T(0);
+#pragma unroll
+          for (int o = 0; o < 7; ++o) kin += kc[o] * w[i + o][jj];
+          if (any_mixed && ((p[j] >= T(0)) != pos0)) {
+            // where p = 0 falls inside a lane, its nodes of the other sign
+            // take the mirrored stencil
+            kin = T(0);
+#pragma unroll
+            for (int o = 0; o < 7; ++o) kin += kcm[o] * w[i + o][jj];
+          }
+          base[i][comp][j] = yv[i][jj] + coef * (kscale[j] * kin + lev[i][j]);
+          asm volatile("" : "+v"(base[i][comp][j]));
+        }
+    }
+  }
+  wave_lds_sync();
+
+  // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p (read
+  // back from LDS: every lane reads only what it wrote)
+  if (a.coup[0][1] != 0.0) {
+    T coup[2][2] = {{T(0), T(a.coup[0][1])}, {T(a.coup[1][0]), T(0)}};
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        T h[NC], cm[NC];
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) h[comp] = s[(i * NC + comp) * LDP + wave_pad(a0 + j)];
+        commutator_mi<2, T>(coup, h, cm);
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) base[i][comp][j] += coef * cm[comp];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < C; ++i)
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp)
+#pragma unroll
+      for (int j = 0; j < K; ++j) asm volatile("" : "+v"(base[i][comp][j]));
+
+  // ---- potential term ----------------------------------------------------
+  // item = lane: transform f = lane / 16 (f & 1: column; f >> 1: 0 for the
+  // packed diagonals (0, 1), 1 for the off-diagonal pair), index lane % 16
+  const int f = lane >> 4, idx = lane & 15;
+  const int col = f & 1, kind = f >> 1;
+  T* const re = s + (col * NC + 2 * kind) * LDP;
+  T* const im = re + LDP;
+
+  // first forward pass: N1-point DFT over stride N2, twiddle
+  {
+    const int n2 = idx;
+    cx<T> x[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) x[n1] = {re[(N2 + 1) * n1 + n2], im[(N2 + 1) * n1 + n2]};
+    SmallDft<N1, 1, T>::run(x);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const cx<T> y = cmul(x[k1], stw[k1 * (N2 + 1) + n2]);
+      re[(N2 + 1) * k1 + n2] = y.re;
+      im[(N2 + 1) * k1 + n2] = y.im;
+    }
+  }
+  wave_lds_sync();
+
+  // r-space multipliers of this item (host-permuted so that the N2 values
+  // of row k1 are contiguous): kind 0 takes the tables of states 0 and 1,
+  // kind 1 the coupling table (stored halved, twice)
+  const int k1 = idx;
+  T mulA[N2], mulB[N2];
+  {
+    const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
+    const rsrc_t rt = make_rsrc(a.mtab, 3u * tbytes);
+    const int qc = min(q0 + col, nq - 1);
+    const unsigned row = ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
+    const unsigned oa = (kind ? 2u : 0u) * tbytes + row, ob = (kind ? 2u : 1u) * tbytes + row;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; k2 += 4) {
+      const Quad<T> qa = buf_load4(rt, oa + k2 * ES, 0, T(0));
+      const Quad<T> qb = buf_load4(rt, ob + k2 * ES, 0, T(0));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        mulA[k2 + j] = qa.v[j];
+        mulB[k2 + j] = qb.v[j];
+      }
+    }
+  }
+  // second forward pass: contiguous N2-point DFT of row k1
+  {
+    T* zr = re + (N2 + 1) * k1;
+    T* zi = im + (N2 + 1) * k1;
+    cx<T> x[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) x[n2] = {zr[n2], zi[n2]};
+    SmallDft<N2, 1, T>::run(x);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      zr[k2] = x[k2].re;
+      zi[k2] = x[k2].im;
+    }
+    // row 0 also stores X[0] in its padding slot, so that the partner of
+    // index m lies at pbase - k2 for every row
+    if (k1 == 0) {
+      zr[N2] = x[0].re;
+      zi[N2] = x[0].im;
+    }
+  }
+  wave_lds_sync();
+
+  // r-space multiplication (position k2 + (N2+1) k1 holds index
+  // m = k1 + N1 k2) and the first inverse pass; every lane reads its own and
+  // its partner row before any lane writes
+  const T c0t = has_up ? T(0) : c0;  // terminator level carries c0 D_p D_p
+  cx<T> yk[N2];
+  {
+    const T* zr = re + (N2 + 1) * k1;
+    const T* zi = im + (N2 + 1) * k1;
+    const int pbase = (k1 == 0) ? N2 : (N2 - 1) + (N2 + 1) * (N1 - k1);
+    const T* pr = re + pbase;
+    const T* pi = im + pbase;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const cx<T> z = {zr[k2], zi[k2]};
+      const cx<T> zp = {pr[-k2], -pi[-k2]};
+      const T e = cdel * ssym[k1 + N1 * k2] + c0t * ssym[NP + k1 + N1 * k2];
+      // Y = -i [ s Z[m] + d conj(Z[-m]) ] + e Z; the coupling transform has
+      // mulA = mulB = g/2, so s = g and d = 0
+      const T sA = mulA[k2] + mulB[k2], dA = mulA[k2] - mulB[k2];
+      const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
+      yk[k2] = {u.im + e * z.re, -u.re + e * z.im};
+    }
+  }
+  SmallDft<N2, -1, T>::run(yk);
+  wave_lds_sync();
+  {
+    T* zr = re + (N2 + 1) * k1;
+    T* zi = im + (N2 + 1) * k1;
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      const cx<T> g = cmulc(yk[n2], stw[k1 * (N2 + 1) + n2]);
+      zr[n2] = g.re;
+      zi[n2] = g.im;
+    }
+  }
+  wave_lds_sync();
+
+  // second inverse pass: N1-point DFTs over stride N2, natural order out
+  {
+    const int n2 = idx;
+    cx<T> x[N1];
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) x[kk] = {re[n2 + (N2 + 1) * kk], im[n2 + (N2 + 1) * kk]};
+    SmallDft<N1, -1, T>::run(x);
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      re[n2 + (N2 + 1) * n1] = x[n1].re;
+      im[n2 + (N2 + 1) * n1] = x[n1].im;
+    }
+  }
+  wave_lds_sync();
+
+  // ---- combine, write, level-0 trace partial -----------------------------
+  const rsrc_t ro = make_rsrc(static_cast<T*>(a.out) + (long long)b * a.member_stride + (long long)n * a.level_stride,
+                              level_bytes);
+  const bool want_trace = (a.partials != nullptr) && (n == 0);
+  double tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    if (q0 + i >= nq) continue;
+    T o[NC][K];
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) {
+      Quad<T> qv;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        o[comp][j] = base[i][comp][j] + coef * s[(i * NC + comp) * LDP + wave_pad(a0 + j)];
+        qv.v[j] = o[comp][j];
+      }
+      buf_store4(qv, ro, qo[i + 3], comp * cbytes);
+    }
+    if (want_trace) {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        tr += a.mu[0][0] * (double)o[0][j] + a.mu[1][1] * (double)o[1][j] + 2.0 * a.mu[0][1] * (double)o[2][j];
+    }
+  }
+  if (want_trace) {
+    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+    if (lane == 0) a.partials[((long long)b * kRespSlots + a.slot) * a.ntiles + pair] = tr;
+  }
+}
+
+template <typename T>
+hipError_t launch_stage_wave(const StageArgs& a, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((stage_wave_kernel<T>), dim3(nblocks), dim3(WavePlan::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace qhfpe

@@ -63,15 +63,18 @@ def test_small_absorption_full_length(precision):
         assert spec_err(I, g["I_abs"]) < 1e-4
 
 
+@pytest.mark.parametrize("tile", [4, 1])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_production_size_parity(precision):
-    """256x256, depth 8, both zetas as one batch (the bench launch), 100 steps."""
+def test_production_size_parity(precision, tile):
+    """256x256, depth 8, both zetas as one batch (the bench launch), 100 steps,
+    with the workgroup (4) and the wave-independent (1) stage variant."""
     g = np.load(os.path.join(GOLDEN, "production_100.npz"))
     w = inputs.PRODUCTION_ABSORPTION
     m = w["model"]
     cols = g["columns"]
-    say(f"production {precision}")
+    say(f"production {precision} tile {tile}")
     P = qhfpe.Propagator(m, batch=len(w["zetas"]), precision=precision)
+    P.set_tile(tile)
     for i, z in enumerate(w["zetas"]):
         P.set_member_bath(i, z, m["gamma"], m["beta"])
     P.init_thermal(w["thermal_omega"])
