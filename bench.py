@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STAGE_SOURCES = ["paper_1706_09590_amd/csrc/stage_kernel.hpp", "paper_1706_09590_amd/csrc/device_common.hpp"]
+STAGE_SOURCES = ["paper_1706_09590_amd/csrc/stage_kernel.hpp", "paper_1706_09590_amd/csrc/stage_wave.hpp",
+                 "paper_1706_09590_amd/csrc/device_common.hpp"]
 
 
 def kernel_source_sha() -> str:
@@ -98,7 +99,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--nsteps", type=int, default=20000, help="RK4 steps per propagation")
     ap.add_argument("--tile", type=int, default=0,
-                    help="cells per thread of the stage kernel (0: autotune before the timed region)")
+                    help="stage tile variant (1: wave per column pair; 2, 4, 8: workgroup tiles with that many "
+                         "columns per thread; 0: autotune before the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
@@ -181,7 +183,7 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
                     avg_launch_us=round(launch_s * 1e6, 3), bytes_per_launch=bytes_per_launch,
-                    cells_per_thread=tile,
+                    tile_variant=tile,
                     kernel_source_sha=kernel_source_sha())
         out = dict(value=updates / wall, wall_s=wall, gpu_s=gpu_s, ms_per_step=1e3 * wall / steps,
                    roofline=roof, resp=resp.cpu().numpy(), spec=[s.cpu().numpy() for s in spec])

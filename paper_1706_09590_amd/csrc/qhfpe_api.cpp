@@ -405,7 +405,7 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->ns = params->n_states;
   h->nc = h->ns * h->ns;
   h->levels = params->depth + 1;
-  h->cpt = cpt_default((int)L.elem, params->n_states);
+  h->cpt = tile_default((int)L.elem, params->n_states, params->np);
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
   // setup tables, computed in FP64 and rounded once to the state precision
@@ -478,7 +478,7 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
 
 int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
   if (int rc = check_handle(h)) return rc;
-  const int c = cells_per_thread == 0 ? cpt_default((int)h->L.elem, h->ns) : cells_per_thread;
+  const int c = cells_per_thread == 0 ? tile_default((int)h->L.elem, h->ns, h->p.np) : cells_per_thread;
   if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c))
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
   h->cpt = c;

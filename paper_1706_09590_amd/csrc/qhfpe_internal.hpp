@@ -51,6 +51,9 @@ inline bool wave_supported(int ns, int np) { return ns == 2 && np == 256; }
 inline bool tile_supported(int elem_bytes, int ns, int np, int code) {
   return code == kTileWave ? wave_supported(ns, np) : cpt_supported(elem_bytes, ns, code);
 }
+inline int tile_default(int elem_bytes, int ns, int np) {
+  return wave_supported(ns, np) ? kTileWave : cpt_default(elem_bytes, ns);
+}
 
 // Arguments of the fused RK-stage kernel (passed by value).
 struct StageArgs {

@@ -132,9 +132,7 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   const T zterm = has_up ? T(0) : zeta;
 
   // ---- local terms, one component at a time ------------------------------
-  // The kinetic window is loaded in node halves for double (two nodes per
-  // 16-byte access), so that one half-window is in flight at a time.
-  constexpr int KH = (sizeof(T) == 8) ? 2 : 4;  // nodes per kinetic pass
+  constexpr int KH = K;  // nodes per kinetic pass (all four: the fastest in both precisions)
   T base[C][NC][K];  // y + coef * (all terms except the potential)
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
