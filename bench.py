@@ -108,6 +108,10 @@ def main():
                     help="also time the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
     ap.add_argument("--two-d-scale", type=int, default=1,
                     help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
+                         "a quarter three-state, 5000 steps, FP32 state)")
+    ap.add_argument("--sweep-steps", type=int, default=0, help="steps of the sweep (0: the workload's 5000)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,10 +227,37 @@ def main():
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
     if args.two_d:
         line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale)
+    if args.sweep:
+        line["uneven_sweep"] = uneven_sweep(args.sweep_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(inputs.model_dict(base, zeta=1.0))
         line["cpu_baseline"] = cb
     print(json.dumps(line, default=float))
+
+
+def uneven_sweep(nsteps: int = 0):
+    """Wall time of the uneven batched sweep: plan (spectral radius and
+    substeps per member, reported apart), then all members as batches of
+    like-shaped members on four concurrent streams, FP32 state, R1 every step."""
+    import numpy as np
+    import torch
+
+    from paper_1706_09590_amd import inputs, sweep
+    w = inputs.UNEVEN_SWEEP
+    nsteps = nsteps or w["nsteps"]
+    members = inputs.uneven_sweep_members(w["n_members"], w["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    subs, batches = sweep.plan(members, w["dt"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=4, batches=batches)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return dict(wall_s=t2 - t1, plan_s=t1 - t0, members=len(members), batches=len(batches), rk4_steps=nsteps,
+                substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
+                cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
+                finite=bool(all(np.all(np.isfinite(r)) for r in R)))
 
 
 def two_d_spectrum(scale: int = 1):

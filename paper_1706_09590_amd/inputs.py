@@ -81,6 +81,27 @@ TWO_D_SPECTRUM = dict(
     n3_steps=4000, stride3=1)
 
 
+# Uneven batched sweep: 256 members on grids 96^2..256^2, depths 4..10, a
+# quarter of them three-state, random Drude baths; 5000 RK4 steps of 0.002
+# (sampled every step; members that need it take RK4 substeps).
+UNEVEN_SWEEP = dict(n_members=256, seed=1706, dt=0.002, nsteps=5000)
+
+
+def uneven_sweep_members(n: int = 256, seed: int = 1706) -> list:
+    """Member i: grid [96, 128, 192, 256][i % 4], depth [4, 6, 8, 10][(i // 4) % 4],
+    three states iff (i // 16) % 4 == 3; drawn in member order from
+    default_rng(seed): zeta = exp(U(ln 0.05, ln 5)), then beta = U(0.5, 3);
+    gamma = 1."""
+    rng = np.random.default_rng(seed)
+    members = []
+    for i in range(n):
+        zeta = float(np.exp(rng.uniform(np.log(0.05), np.log(5.0))))
+        beta = float(rng.uniform(0.5, 3.0))
+        members.append(dict(grid=[96, 128, 192, 256][i % 4], depth=[4, 6, 8, 10][(i // 4) % 4],
+                            n_states=3 if (i // 16) % 4 == 3 else 2, zeta=zeta, gamma=1.0, beta=beta))
+    return members
+
+
 def model_dict(base: dict, **over) -> dict:
     m = copy.deepcopy(base)
     m.update(over)

@@ -1,0 +1,152 @@
+"""Uneven batched sweeps: many independent propagations with different grids,
+depths, state counts and baths, run as batches of like-shaped members.
+
+The linear-absorption protocol of Sec. III (thermal state, impulsive mu^x,
+R1(t) = (i/hbar) Tr{mu W^(0)(t)}, Eq. (R1)) is run for every member.
+Members that share a grid, a depth, a state count and a number of RK4
+substeps form one batch (one library handle, one launch per stage); the
+batches run concurrently, each on its own stream from its own host thread
+(the library calls release the interpreter lock).
+
+RK4 is only stable for dt |lambda| below about 2.8; members with strong,
+hot baths need substeps.  Each member's spectral radius is estimated by
+power iteration with the library's operator (qhfpe_apply_rhs, FP64) and the
+member takes ceil(dt rho / 2.5) substeps of dt / substeps; the response is
+still sampled every dt.
+
+This module only sequences library calls; all arithmetic runs in the HIP
+library.
+"""
+
+from __future__ import annotations
+
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from . import inputs, qhfpe
+
+RK4_MARGIN = 2.5  # dt * rho allowed per substep (RK4 is stable to about 2.8)
+
+
+def member_model(member: dict, dt: float) -> dict:
+    """Model dict of one sweep member (its bath in zeta/beta)."""
+    n = member["grid"]
+    ns = member["n_states"]
+    poly = inputs.two_state_surfaces(0.3) if ns == 2 else inputs.three_state_surfaces(0.3, 0.2)
+    mu = [[0.0, 1.0], [1.0, 0.0]] if ns == 2 else [[0.0, 1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0]]
+    return inputs.model_dict(inputs.SMALL_ABSORPTION["model"], n_states=ns, nq=n, np=n, depth=member["depth"],
+                             zeta=member["zeta"], gamma=member["gamma"], beta=member["beta"], poly=poly, mu=mu,
+                             dt=dt)
+
+
+def _shape_key(model: dict):
+    return (model["n_states"], model["nq"], model["np"], model["depth"], model["q_min"], model["q_max"],
+            model["p_min"], model["p_max"])
+
+
+def spectral_radius(model: dict, baths, iters: int = 40, seed: int = 7, device=None, renorm_every: int = 8):
+    """Power-iteration estimate of the spectral radius of L for each bath
+    (zeta, gamma, beta) on the grid of `model`: ||L^(k+1) W|| / ||L^k W||
+    after `iters` applications, from a seeded random Hermitian hierarchy.
+    Returns a float64 array, one value per bath."""
+    import torch
+    B = len(baths)
+    P = qhfpe.Propagator(model, batch=B, precision="fp64", device=device)
+    try:
+        for i, (z, g, b) in enumerate(baths):
+            P.set_member_bath(i, z, g, b)
+        W = inputs.random_hierarchy(model["depth"], model["n_states"], model["nq"], model["np"], seed=seed,
+                                    smooth=False)
+        P.set_state(torch.from_numpy(np.broadcast_to(W, (B,) + W.shape).copy()), phase=0)
+        rho = np.zeros(B)
+        for k in range(iters):
+            r = P.residual()
+            rho = r[:, 0] / np.maximum(r[:, 1], 1e-300)
+            P.apply_rhs()
+            if (k + 1) % renorm_every == 0:
+                # rescale every member to unit norm so the iterates stay finite
+                S = P.get_state()
+                n = torch.linalg.vector_norm(S.reshape(B, -1), dim=1).clamp_min(1e-300)
+                P.set_state(S / n.view((B,) + (1,) * (S.dim() - 1)), phase=P.phase)
+        return rho
+    finally:
+        P.close()
+
+
+def substeps_for(dt: float, rho, margin: float = RK4_MARGIN):
+    return np.maximum(1, np.ceil(dt * np.asarray(rho) / margin)).astype(int)
+
+
+def plan(members, dt: float, estimate_iters: int = 40, device=None):
+    """Substeps per member and the batches: list of (model, [member ids], substeps)."""
+    by_shape = {}
+    for i, m in enumerate(members):
+        mod = member_model(m, dt)
+        by_shape.setdefault(_shape_key(mod), (mod, []))[1].append(i)
+    subs = np.ones(len(members), dtype=int)
+    for mod, ids in by_shape.values():
+        rho = spectral_radius(mod, [(members[i]["zeta"], members[i]["gamma"], members[i]["beta"]) for i in ids],
+                              iters=estimate_iters, device=device)
+        subs[ids] = substeps_for(dt, rho)
+    batches = []
+    for mod, ids in by_shape.values():
+        for s in sorted(set(subs[ids].tolist())):
+            batches.append((mod, [i for i in ids if subs[i] == s], int(s)))
+    return subs, batches
+
+
+def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams: int = 4, batches=None,
+              thermal_omega: float = 1.0, device=None):
+    """R1(t) for every member, sampled every dt for nsteps steps.
+
+    batches: from plan() (computed here if None).  Returns (list of complex128
+    numpy arrays [nsteps+1] in member order, info dict)."""
+    import torch
+    qhfpe.lib()  # load the library before the worker threads start
+    if batches is None:
+        _, batches = plan(members, dt, device=device)
+    results = [None] * len(members)
+    dev = torch.device(device if device is not None else "cuda")
+    lock = threading.Lock()
+    counts = {"cell_updates": 0}
+
+    def run_batch(job):
+        mod, ids, subs = job
+        s = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(s):
+            P = qhfpe.Propagator(inputs.model_dict(mod, dt=dt / subs), batch=len(ids), precision=precision,
+                                 device=dev, stream=s)
+            try:
+                for j, i in enumerate(ids):
+                    m = members[i]
+                    P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
+                P.init_thermal(thermal_omega)
+                P.apply_dipole()
+                tr = P.step(nsteps * subs, subs)
+                R1 = ((1j / mod.get("hbar", 1.0)) * tr).cpu().numpy()
+            finally:
+                P.close()
+        cells = (mod["depth"] + 1) * mod["nq"] * mod["np"]
+        with lock:
+            for j, i in enumerate(ids):
+                results[i] = R1[j]
+            counts["cell_updates"] += cells * len(ids) * nsteps * subs
+        return len(ids)
+
+    # largest batches first, so that the small ones fill in at the end
+    order = sorted(batches, key=lambda b: -(b[0]["depth"] + 1) * b[0]["nq"] * b[0]["np"] * len(b[1]) * b[2])
+    with ThreadPoolExecutor(max_workers=max(1, int(streams))) as ex:
+        list(ex.map(run_batch, order))
+    info = dict(batches=len(batches), cell_updates=counts["cell_updates"])
+    return results, info
+
+
+def sweep_cell_updates(members, nsteps: int, substeps) -> int:
+    """Cell-updates (one cell of every level, all components, one RK4 step) of a sweep."""
+    return int(sum((m["depth"] + 1) * m["grid"] ** 2 * nsteps * int(s) for m, s in zip(members, substeps)))
+
+
+__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "run_sweep", "sweep_cell_updates",
+           "RK4_MARGIN"]

@@ -1,0 +1,79 @@
+"""The uneven batched sweep on the GPU: the spectral-radius estimate behind
+the substeps against the eigenvalues of the oracle's dense operator, and the
+grouped, multi-stream run against the FP64 oracle member by member."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import oracle_model
+from oracle import qhfpe_oracle as O
+from paper_1706_09590_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1706_09590_amd import sweep  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dense_operator(m):
+    """Columns L e_k of the oracle's RHS on every unit vector (complex-linear)."""
+    shape = (m.depth + 1, m.n_states, m.n_states, m.nq, m.np_)
+    n = int(np.prod(shape))
+    A = np.zeros((n, n), dtype=complex)
+    for k in range(n):
+        e = np.zeros(n, dtype=complex)
+        e[k] = 1.0
+        A[:, k] = O.rhs(m, e.reshape(shape)).ravel()
+    return A
+
+
+@pytest.mark.parametrize("ns,zeta,beta", [(2, 0.5, 1.0), (2, 4.0, 0.6), (3, 1.5, 2.0)])
+def test_spectral_radius_matches_dense_eigenvalues(ns, zeta, beta):
+    member = dict(grid=8, depth=1, n_states=ns, zeta=zeta, gamma=1.0, beta=beta)
+    d = sweep.member_model(member, 0.002)
+    d.update(nq=5, np=8)
+    say(f"spectral radius ns={ns} zeta={zeta}")
+    rho_dense = np.max(np.abs(np.linalg.eigvals(dense_operator(oracle_model(d)))))
+    rho = sweep.spectral_radius(d, [(zeta, 1.0, beta)], iters=200)[0]
+    assert rho == pytest.approx(rho_dense, rel=0.05)
+
+
+def test_grouped_sweep_matches_the_oracle_per_member():
+    # small uneven members: three grids, three depths, two and three states,
+    # one member forced to two substeps
+    rng = np.random.default_rng(11)
+    members = []
+    for i, (g, dep, ns) in enumerate([(16, 1, 2), (16, 1, 2), (24, 2, 2), (24, 2, 3), (32, 3, 2), (32, 3, 2)]):
+        members.append(dict(grid=g, depth=dep, n_states=ns, zeta=float(rng.uniform(0.1, 2.0)), gamma=1.0,
+                            beta=float(rng.uniform(0.5, 3.0))))
+    dt, nsteps = 0.005, 12
+    subs, batches = sweep.plan(members, dt)
+    say(f"substeps {list(subs)}")
+    # split member 5 into its own batch with one more substep than planned
+    subs = [int(x) for x in subs]
+    subs[5] += 1
+    batches = [(mod, [i for i in ids if i != 5], s) for mod, ids, s in batches if [i for i in ids if i != 5]]
+    batches.append((sweep.member_model(members[5], dt), [5], subs[5]))
+    say("grouped sweep fp64")
+    R, info = sweep.run_sweep(members, nsteps, dt, precision="fp64", streams=3, batches=batches)
+    assert info["batches"] == len(batches)
+    for i, mem in enumerate(members):
+        m = oracle_model(inputs.model_dict(sweep.member_model(mem, dt), dt=dt / subs[i]))
+        W0 = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
+        _, tr = O.propagate(m, W0, nsteps * subs[i], subs[i])
+        ref = (1j / m.hbar) * tr
+        err = np.linalg.norm(R[i] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10, (i, err)
+    say("grouped sweep fp32")
+    R32, _ = sweep.run_sweep(members, nsteps, dt, precision="fp32", streams=2, batches=batches)
+    for i in range(len(members)):
+        assert np.linalg.norm(R32[i] - R[i]) / np.linalg.norm(R[i]) < 1e-4

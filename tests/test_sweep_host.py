@@ -1,0 +1,42 @@
+"""Host logic of the uneven batched sweep: member sampling and substeps."""
+
+import collections
+
+import numpy as np
+
+from paper_1706_09590_amd import inputs, sweep
+
+
+def test_uneven_sweep_members_follow_the_sampling_rule():
+    m = inputs.uneven_sweep_members()
+    assert len(m) == 256
+    assert sum(x["n_states"] == 3 for x in m) == 64
+    for i, x in enumerate(m):
+        assert x["grid"] == [96, 128, 192, 256][i % 4]
+        assert x["depth"] == [4, 6, 8, 10][(i // 4) % 4]
+        assert (x["n_states"] == 3) == ((i // 16) % 4 == 3)
+        assert 0.05 <= x["zeta"] <= 5.0 and 0.5 <= x["beta"] <= 3.0 and x["gamma"] == 1.0
+    # every (grid, depth) pair appears 16 times, 4 of them three-state
+    c = collections.Counter((x["grid"], x["depth"], x["n_states"]) for x in m)
+    assert set(c.values()) == {12, 4}
+    # draws in member order: zeta then beta from one generator
+    rng = np.random.default_rng(1706)
+    z0 = float(np.exp(rng.uniform(np.log(0.05), np.log(5.0))))
+    b0 = float(rng.uniform(0.5, 3.0))
+    assert (m[0]["zeta"], m[0]["beta"]) == (z0, b0)
+    assert inputs.uneven_sweep_members() == m
+
+
+def test_substeps_rule():
+    dt = 0.002
+    assert list(sweep.substeps_for(dt, [0.0, 1249.0, 1250.0, 1251.0, 6000.0])) == [1, 1, 1, 2, 5]
+
+
+def test_member_model_shapes():
+    m = inputs.uneven_sweep_members()
+    for i in (0, 5, 63, 255):
+        mod = sweep.member_model(m[i], 0.002)
+        assert mod["nq"] == mod["np"] == m[i]["grid"]
+        assert mod["depth"] == m[i]["depth"] and mod["n_states"] == m[i]["n_states"]
+        assert len(mod["poly"]) == mod["n_states"] and len(mod["mu"]) == mod["n_states"]
+        assert mod["zeta"] == m[i]["zeta"] and mod["beta"] == m[i]["beta"]
