@@ -115,9 +115,9 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
 /* Tile variant of the fused RK stage.  2, 4, 8: each thread of a stage
  * workgroup owns cells_per_thread consecutive q columns (2, 4 or 8 for FP32
  * two-state; 2 or 4 for FP64 two-state and FP32 three-state; 2 for FP64
- * three-state).  1: the wave-independent variant, one 64-lane wave per pair
- * of q columns, each lane holding np/64 consecutive p nodes (two states and
- * np = 256 only).  0 = default: 1 where available, else 4 (2 for FP64
+ * three-state).  1: the wave-independent variant, one 64-lane wave per
+ * 512/np q columns, each lane holding np/64 consecutive p nodes (two states
+ * and np = 128 or 256 only).  0 = default: 1 where available, else 4 (2 for FP64
  * three-state); it is also the variant at create.  Variants compute the same operations per
  * cell; results agree to rounding (the compiled instruction order and the
  * grouping of the trace partial sums differ).  QHFPE_EUNSUPPORTED if the

@@ -190,12 +190,12 @@ void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<
 }
 
 // The multiplier tables of the wave variant in one array, each q row
-// permuted so that the 16 values m = k1 + 16 k2 (k2 = 0..15) of row k1 are
-// contiguous; the coupling table is stored halved (the kernel treats it as
+// permuted so that the n2 values m = k1 + n1 k2 (k2 = 0..n2-1) of row k1
+// are contiguous; the coupling table is stored halved (the kernel treats it as
 // a pair of equal diagonal multipliers).
-void wave_tables(const qhfpe_params& p, const std::vector<double>& dtab, const std::vector<double>& gtab,
-                 std::vector<double>& mtab) {
-  const int nq = p.nq, np = p.np, n1 = 16, n2 = np / 16;
+void wave_tables(const qhfpe_params& p, int n1, int n2, const std::vector<double>& dtab,
+                 const std::vector<double>& gtab, std::vector<double>& mtab) {
+  const int nq = p.nq, np = p.np;
   const size_t plane = (size_t)nq * np;
   mtab.assign(3 * plane, 0.0);
   for (int t = 0; t < 3; ++t)
@@ -252,7 +252,7 @@ struct qhfpe_handle {
   int cpt = 4;  // stage tile variant (cells per thread along q)
 
   bool wave() const { return cpt == kTileWave; }
-  int tq() const { return wave() ? 2 : plan_groups(p.np) * cpt; }
+  int tq() const { return wave() ? wave_columns(p.np) : plan_groups(p.np) * cpt; }
   int ntiles() const { return (p.nq + tq() - 1) / tq(); }
   double dq = 0, dp = 0;
 
@@ -323,7 +323,8 @@ struct qhfpe_handle {
   hipError_t launch(const StageArgs& a) const {
     const int nblocks = a.nblocks_padded;
     if (wave())
-      return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(a, nblocks, stream) : launch_stage_wave_f32(a, nblocks, stream);
+      return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(p.np, a, nblocks, stream)
+                                       : launch_stage_wave_f32(p.np, a, nblocks, stream);
     if (p.precision == QHFPE_FP64)
       return ns == 2 ? launch_stage_f64_ns2(p.np, cpt, a, nblocks, stream)
                      : launch_stage_f64_ns3(p.np, cpt, a, nblocks, stream);
@@ -414,7 +415,7 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   stencil_symbols(params->np, h->dp, sym);
   multiplier_tables(*params, h->dq, h->dp, dt, gt);
   std::vector<double> mt;
-  if (wave_supported(params->n_states, params->np)) wave_tables(*params, dt, gt, mt);
+  if (wave_supported(params->n_states, params->np)) wave_tables(*params, L.n1, L.n2, dt, gt, mt);
   std::vector<double> bath((size_t)params->batch * kBathStride);
   double bc[kBathStride];
   bath_constants(*params, params->zeta, params->gamma, params->beta, bc);

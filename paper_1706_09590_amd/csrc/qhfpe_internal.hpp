@@ -47,7 +47,9 @@ inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns =
 // wave per pair of q columns, two states and np = 256 only.
 constexpr int kTileWave = 1;
 constexpr int kWaveTasksPerBlock = 4;  // waves per workgroup of the wave variant
-inline bool wave_supported(int ns, int np) { return ns == 2 && np == 256; }
+inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
+// q columns per task of the wave variant (a lane holds np / 64 p nodes)
+constexpr int wave_columns(int np) { return 512 / np; }
 inline bool tile_supported(int elem_bytes, int ns, int np, int code) {
   return code == kTileWave ? wave_supported(ns, np) : cpt_supported(elem_bytes, ns, code);
 }
@@ -64,7 +66,7 @@ struct StageArgs {
   const void* twiddle2;  // [n1][n2+1] complex exp(+2 pi i (n2 k1 mod np)/np), state precision
   const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
   const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
-  const void* mtab;      // wave variant: [3][nq][np/16][16] = dtab 0, dtab 1, gtab / 2, entry (k1, k2) at m = k1 + 16 k2
+  const void* mtab;      // wave variant: [3][nq][16][np/16] = dtab 0, dtab 1, gtab / 2, entry (k1, k2) at m = k1 + 16 k2
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
   int slot;
@@ -88,8 +90,8 @@ hipError_t launch_stage_f64_ns2(int np, int cpt, const StageArgs& a, int nblocks
 hipError_t launch_stage_f64_ns3(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_stage_f32_ns2(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_stage_f32_ns3(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_stage_wave_f64(const StageArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_stage_wave_f32(const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_wave_f64(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_wave_f32(int np, const StageArgs& a, int nblocks, hipStream_t s);
 
 // Pointwise and reduction kernels (aux_kernels.hip).
 struct DipoleMu {

@@ -6,7 +6,7 @@ namespace qhfpe {
 hipError_t launch_stage_f32_ns2(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s) {
   return launch_stage<float, 2>(np, cpt, a, nblocks, s);
 }
-hipError_t launch_stage_wave_f32(const StageArgs& a, int nblocks, hipStream_t s) {
-  return launch_stage_wave<float>(a, nblocks, s);
+hipError_t launch_stage_wave_f32(int np, const StageArgs& a, int nblocks, hipStream_t s) {
+  return launch_stage_wave<float>(np, a, nblocks, s);
 }
 }  // namespace qhfpe

@@ -1,25 +1,27 @@
 // Fused RK4 stage, wave-independent variant for two electronic states and
-// np = 256:  out = y + coef * L v  with the same operator as stage_kernel.hpp
-// (Eq. (heom) of Ikeda & Tanimura (2017) with one Drude exponential and
-// V(q) = q, closed by Eq. (GMFP); potential term of Eq.
+// np = 128 or 256:  out = y + coef * L v  with the same operator as
+// stage_kernel.hpp (Eq. (heom) of Ikeda & Tanimura (2017) with one Drude
+// exponential and V(q) = q, closed by Eq. (GMFP); potential term of Eq.
 // (quantum-liouvillian) through the DFT along p; Sec. III discretisation).
 //
-// One wave owns a whole task: two neighbouring q columns of one level of one
-// batch member, all four packed components.  Lane l holds the p nodes
-// 4l .. 4l+3 of both columns.  The waves of a workgroup share only the
-// twiddle and symbol tables (loaded once behind the single workgroup
-// barrier); every later step orders its LDS accesses within the wave, so a
-// wave waiting for memory never stalls another.
+// One wave owns a whole task: C neighbouring q columns (C = 512 / np) of one
+// level of one batch member, all four packed components.  Lane l holds the
+// K = np / 64 consecutive p nodes K l .. K l + K - 1 of every column.  The
+// waves of a workgroup share only the twiddle and symbol tables (loaded once
+// behind the single workgroup barrier); every later step orders its LDS
+// accesses within the wave, so a wave waiting for memory never stalls
+// another.
 //
-//  - kinetic -(p/m) D_q: 5th-order upwind over an 8-column q window;
+//  - kinetic -(p/m) D_q: 5th-order upwind over a (C + 6)-column q window;
 //  - D_p of the level field g: the stencil neighbours p +- 1, +- 2 of a
-//    lane's four nodes are its own or the neighbouring lanes' (DPP wave
+//    lane's nodes are its own or the neighbouring lanes' (DPP wave
 //    rotations; the p grid is periodic and one column fills the wave);
-//  - potential term: four complex 256-point transforms per task (the two
-//    real diagonals of a column packed into one, the off-diagonal pair in
-//    another), 16 x 16 two-pass FFT with one radix-16 item per lane and
-//    pass, r-space multiply in place (all lanes read their own and partner
-//    rows before any lane writes), inverse transform;
+//  - potential term: 2 C complex np-point transforms per task (the two real
+//    diagonals of a column packed into one, the off-diagonal pair in
+//    another), two-pass FFT np = N1 N2 with 2 C N2 / 64 and 2 C N1 / 64 items
+//    per lane in the two passes (every lane busy), r-space multiply in place
+//    (all lanes read their own and partner rows before any lane writes),
+//    inverse transform;
 //  - constant diabatic coupling: pointwise commutator in p.
 #pragma once
 
@@ -29,25 +31,55 @@
 
 namespace qhfpe {
 
+template <int NP_>
 struct WavePlan {
-  static constexpr int NP = 256, N1 = 16, N2 = 16;
-  static constexpr int K = 4;    // p nodes per lane
-  static constexpr int C = 2;    // q columns per task
-  static constexpr int NC = 4;   // packed components (two states)
+  static constexpr int NP = NP_;
+  static constexpr int N1 = FftSplit<NP>::N1, N2 = FftSplit<NP>::N2;
+  static constexpr int K = NP / 64;            // p nodes per lane
+  static constexpr int C = wave_columns(NP);   // q columns per task
+  static constexpr int NC = 4;                 // packed components (two states)
+  static constexpr int NF = 2 * C;             // complex transforms per task
+  static constexpr int I1 = NF * N2 / 64;      // items per lane, stride-N2 passes
+  static constexpr int I2 = NF * N1 / 64;      // items per lane, contiguous passes
   static constexpr int WPB = kWaveTasksPerBlock;  // waves per workgroup
   static constexpr int NT = 64 * WPB;
   static constexpr int LDP0 = NP + NP / N2;
   static constexpr int LDP = LDP0 + ((4 - LDP0 % 16) + 16) % 16;
+  static_assert(K >= 2 && NF * N2 % 64 == 0 && NF * N1 % 64 == 0 && N2 % 4 == 0, "wave plan");
 };
 
-// Position of p node a in a padded LDS column (one pad element per N2 block).
-__device__ __forceinline__ constexpr int wave_pad(int a) { return a + a / WavePlan::N2; }
+// M consecutive elements per lane stored with one or two 16-byte (or one
+// 8-byte) accesses; voff aligned to the access size.
+template <int M>
+__device__ __forceinline__ void buf_store_n(const float* v, rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (M == 2) {
+    using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    const qhfpe_f2 x = {v[0], v[1]};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, (int)voff, (int)soff, 0);
+  } else {
+    static_assert(M == 4, "2 or 4 floats");
+    buf_store4(Quad<float>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
+  }
+}
+template <int M>
+__device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (M == 2) {
+    using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+    const qhfpe_d2 x = {v[0], v[1]};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
+  } else {
+    static_assert(M == 4, "2 or 4 doubles");
+    buf_store4(Quad<double>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
+  }
+}
 
-template <typename T>
-__global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a) {
-  using W = WavePlan;
-  constexpr int NP = W::NP, N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
+template <typename T, int NP>
+__global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageArgs a) {
+  using W = WavePlan<NP>;
+  constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
+  constexpr int I1 = W::I1, I2 = W::I2;
   constexpr int LDP = W::LDP;
+  auto pad = [](int x) { return x + x / N2; };  // padded position of p node x in a column
   __shared__ T sbuf[WPB][C * NC * LDP];  // per wave: v tile, transformed in place
   __shared__ cx<T> stw[N1 * (N2 + 1)];   // w^(n2 k1), row k1 padded to N2 + 1
   __shared__ T ssym[2 * NP];             // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
@@ -62,17 +94,17 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   // scalar registers instead of per-lane loops over descriptor values
   const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nq = a.nq;
-  const int npairs = a.ntiles;  // tasks per level = column pairs
+  const int ntiles = a.ntiles;  // tasks per level = groups of C columns
   const int L = a.depth + 1;
-  const int ntasks = npairs * L * a.batch;
+  const int ntasks = ntiles * L * a.batch;
   // levels fastest, as in stage_kernel: the tasks of all levels of one
-  // column pair run together and share their level neighbours through L2
+  // column group run together and share their level neighbours through L2
   const int task = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
   if (task >= ntasks) return;
   const int n = task % L;
-  const int pair = (task / L) % npairs;
-  const int b = task / (L * npairs);
-  const int q0 = 2 * pair;
+  const int tile = (task / L) % ntiles;
+  const int b = task / (L * ntiles);
+  const int q0 = C * tile;
   T* const s = sbuf[wid];
 
   constexpr unsigned ES = sizeof(T);
@@ -118,7 +150,7 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   const bool mixed = (p[K - 1] >= T(0)) != pos0;
   const bool any_mixed = __any(mixed);
 
-  // byte offsets of the q columns q0-3 .. q0+4 at this lane's first node;
+  // byte offsets of the q columns q0-3 .. q0+C+2 at this lane's first node;
   // columns outside the grid point past the end of every level (read as 0)
   constexpr unsigned kGhost = 0x7fffff00u;
   unsigned qo[C + 6];
@@ -132,36 +164,35 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   const T zterm = has_up ? T(0) : zeta;
 
   // ---- local terms, one component at a time ------------------------------
-  constexpr int KH = K;  // nodes per kinetic pass (all four: the fastest in both precisions)
   T base[C][NC][K];  // y + coef * (all terms except the potential)
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     if (comp > 0) __builtin_amdgcn_sched_barrier(0);
     const unsigned so = comp * cbytes;
-    // level field and level terms at all four nodes of both columns
+    // level field and level terms at the lane's nodes of every column
     T lev[C][K];
     {
-      Quad<T> up[C], dn[C], wc[C];
+      T up[C][K], dn[C][K], wc[C][K];
 #pragma unroll
       for (int i = 0; i < C; ++i) {
-        wc[i] = buf_load4(rn, qo[i + 3], so, T(0));
-        up[i] = buf_load4(ru, qo[i + 3], so, T(0));
-        dn[i] = buf_load4(rd, qo[i + 3], so, T(0));
+        buf_load_n<K>(rn, qo[i + 3], so, wc[i]);
+        buf_load_n<K>(ru, qo[i + 3], so, up[i]);
+        buf_load_n<K>(rd, qo[i + 3], so, dn[i]);
       }
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         T g[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-          const T w0 = wc[i].v[j];
+          const T w0 = wc[i][j];
           // field differentiated once along p:
           //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
           // (the absent neighbour levels read as zero; n gamma = 0 at n = 0)
-          g[j] = up[i].v[j] + (zterm * p[j]) * w0 + (ng * c0) * dn[i].v[j];
-          lev[i][j] = -ng * w0 + (ng * zeta * p[j]) * dn[i].v[j];
-          s[(i * NC + comp) * LDP + wave_pad(a0 + j)] = w0;
+          g[j] = up[i][j] + (zterm * p[j]) * w0 + (ng * c0) * dn[i][j];
+          lev[i][j] = -ng * w0 + (ng * zeta * p[j]) * dn[i][j];
+          s[(i * NC + comp) * LDP + pad(a0 + j)] = w0;
         }
-        // D_p g: nodes a0-2, a0-1 come from the previous lane, a0+4, a0+5
+        // D_p g: nodes a0-2, a0-1 come from the previous lane, a0+K, a0+K+1
         // from the next one (periodic in p: one column spans the whole wave)
         T e[K + 4];
         e[0] = lane_prev(g[K - 2]);
@@ -179,31 +210,27 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
       }
     }
     // kinetic term and the base state
+    {
+      T w[C + 6][K], yv[C][K];
 #pragma unroll
-    for (int h = 0; h < K / KH; ++h) {
-      if (h > 0) __builtin_amdgcn_sched_barrier(0);
-      const unsigned ho = h * KH * ES;
-      T w[C + 6][KH], yv[C][KH];
+      for (int t = 0; t < C + 6; ++t) buf_load_n<K>(rn, qo[t], so, w[t]);
 #pragma unroll
-      for (int t = 0; t < C + 6; ++t) buf_load_n<KH>(rn, qo[t] + ho, so, w[t]);
-#pragma unroll
-      for (int i = 0; i < C; ++i) buf_load_n<KH>(ry, qo[i + 3] + ho, so, yv[i]);
+      for (int i = 0; i < C; ++i) buf_load_n<K>(ry, qo[i + 3], so, yv[i]);
 #pragma unroll
       for (int i = 0; i < C; ++i)
 #pragma unroll
-        for (int jj = 0; jj < KH; ++jj) {
-          const int j = h * KH + jj;
+        for (int j = 0; j < K; ++j) {
           T kin = T(0);
 #pragma unroll
-          for (int o = 0; o < 7; ++o) kin += kc[o] * w[i + o][jj];
+          for (int o = 0; o < 7; ++o) kin += kc[o] * w[i + o][j];
           if (any_mixed && ((p[j] >= T(0)) != pos0)) {
             // where p = 0 falls inside a lane, its nodes of the other sign
             // take the mirrored stencil
             kin = T(0);
 #pragma unroll
-            for (int o = 0; o < 7; ++o) kin += kcm[o] * w[i + o][jj];
+            for (int o = 0; o < 7; ++o) kin += kcm[o] * w[i + o][j];
           }
-          base[i][comp][j] = yv[i][jj] + coef * (kscale[j] * kin + lev[i][j]);
+          base[i][comp][j] = yv[i][j] + coef * (kscale[j] * kin + lev[i][j]);
           asm volatile("" : "+v"(base[i][comp][j]));
         }
     }
@@ -220,7 +247,7 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
       for (int j = 0; j < K; ++j) {
         T h[NC], cm[NC];
 #pragma unroll
-        for (int comp = 0; comp < NC; ++comp) h[comp] = s[(i * NC + comp) * LDP + wave_pad(a0 + j)];
+        for (int comp = 0; comp < NC; ++comp) h[comp] = s[(i * NC + comp) * LDP + pad(a0 + j)];
         commutator_mi<2, T>(coup, h, cm);
 #pragma unroll
         for (int comp = 0; comp < NC; ++comp) base[i][comp][j] += coef * cm[comp];
@@ -234,16 +261,18 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
       for (int j = 0; j < K; ++j) asm volatile("" : "+v"(base[i][comp][j]));
 
   // ---- potential term ----------------------------------------------------
-  // item = lane: transform f = lane / 16 (f & 1: column; f >> 1: 0 for the
-  // packed diagonals (0, 1), 1 for the off-diagonal pair), index lane % 16
-  const int f = lane >> 4, idx = lane & 15;
-  const int col = f & 1, kind = f >> 1;
-  T* const re = s + (col * NC + 2 * kind) * LDP;
-  T* const im = re + LDP;
+  // transform f (0 .. 2C-1): column f % C; f / C = 0 for the packed
+  // diagonals (0, 1), 1 for the off-diagonal pair.  Its real part is the
+  // LDS column of component 2 (f / C), its imaginary part the next one.
+  auto re_of = [&](int f) { return s + ((f % C) * NC + 2 * (f / C)) * LDP; };
 
-  // first forward pass: N1-point DFT over stride N2, twiddle
-  {
-    const int n2 = idx;
+  // first forward pass: N1-point DFTs over stride N2, twiddle
+#pragma unroll
+  for (int t = 0; t < I1; ++t) {
+    const int item = lane + 64 * t;
+    const int n2 = item % N2;
+    T* const re = re_of(item / N2);
+    T* const im = re + LDP;
     cx<T> x[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) x[n1] = {re[(N2 + 1) * n1 + n2], im[(N2 + 1) * n1 + n2]};
@@ -257,32 +286,41 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   }
   wave_lds_sync();
 
-  // r-space multipliers of this item (host-permuted so that the N2 values
-  // of row k1 are contiguous): kind 0 takes the tables of states 0 and 1,
-  // kind 1 the coupling table (stored halved, twice)
-  const int k1 = idx;
-  T mulA[N2], mulB[N2];
+  // r-space multipliers of this lane's items (host-permuted so that the N2
+  // values of row k1 are contiguous): the packed diagonals take the tables
+  // of states 0 and 1, the coupling transform the coupling table (stored
+  // halved, twice)
+  T mulA[I2][N2], mulB[I2][N2];
   {
     const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
     const rsrc_t rt = make_rsrc(a.mtab, 3u * tbytes);
-    const int qc = min(q0 + col, nq - 1);
-    const unsigned row = ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
-    const unsigned oa = (kind ? 2u : 0u) * tbytes + row, ob = (kind ? 2u : 1u) * tbytes + row;
 #pragma unroll
-    for (int k2 = 0; k2 < N2; k2 += 4) {
-      const Quad<T> qa = buf_load4(rt, oa + k2 * ES, 0, T(0));
-      const Quad<T> qb = buf_load4(rt, ob + k2 * ES, 0, T(0));
+    for (int t = 0; t < I2; ++t) {
+      const int item = lane + 64 * t;
+      const int f = item / N1, k1 = item % N1;
+      const int kind = f / C;
+      const int qc = min(q0 + f % C, nq - 1);
+      const unsigned row = ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
+      const unsigned oa = (kind ? 2u : 0u) * tbytes + row, ob = (kind ? 2u : 1u) * tbytes + row;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        mulA[k2 + j] = qa.v[j];
-        mulB[k2 + j] = qb.v[j];
+      for (int k2 = 0; k2 < N2; k2 += 4) {
+        const Quad<T> qa = buf_load4(rt, oa + k2 * ES, 0, T(0));
+        const Quad<T> qb = buf_load4(rt, ob + k2 * ES, 0, T(0));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          mulA[t][k2 + j] = qa.v[j];
+          mulB[t][k2 + j] = qb.v[j];
+        }
       }
     }
   }
-  // second forward pass: contiguous N2-point DFT of row k1
-  {
-    T* zr = re + (N2 + 1) * k1;
-    T* zi = im + (N2 + 1) * k1;
+  // second forward pass: contiguous N2-point DFTs of row k1
+#pragma unroll
+  for (int t = 0; t < I2; ++t) {
+    const int item = lane + 64 * t;
+    const int k1 = item % N1;
+    T* const zr = re_of(item / N1) + (N2 + 1) * k1;
+    T* const zi = zr + LDP;
     cx<T> x[N2];
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) x[n2] = {zr[n2], zi[n2]};
@@ -303,10 +341,15 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
 
   // r-space multiplication (position k2 + (N2+1) k1 holds index
   // m = k1 + N1 k2) and the first inverse pass; every lane reads its own and
-  // its partner row before any lane writes
+  // its partner rows before any lane writes
   const T c0t = has_up ? T(0) : c0;  // terminator level carries c0 D_p D_p
-  cx<T> yk[N2];
-  {
+  cx<T> yk[I2][N2];
+#pragma unroll
+  for (int t = 0; t < I2; ++t) {
+    const int item = lane + 64 * t;
+    const int k1 = item % N1;
+    const T* const re = re_of(item / N1);
+    const T* const im = re + LDP;
     const T* zr = re + (N2 + 1) * k1;
     const T* zi = im + (N2 + 1) * k1;
     const int pbase = (k1 == 0) ? N2 : (N2 - 1) + (N2 + 1) * (N1 - k1);
@@ -319,19 +362,22 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
       const T e = cdel * ssym[k1 + N1 * k2] + c0t * ssym[NP + k1 + N1 * k2];
       // Y = -i [ s Z[m] + d conj(Z[-m]) ] + e Z; the coupling transform has
       // mulA = mulB = g/2, so s = g and d = 0
-      const T sA = mulA[k2] + mulB[k2], dA = mulA[k2] - mulB[k2];
+      const T sA = mulA[t][k2] + mulB[t][k2], dA = mulA[t][k2] - mulB[t][k2];
       const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
-      yk[k2] = {u.im + e * z.re, -u.re + e * z.im};
+      yk[t][k2] = {u.im + e * z.re, -u.re + e * z.im};
     }
+    SmallDft<N2, -1, T>::run(yk[t]);
   }
-  SmallDft<N2, -1, T>::run(yk);
   wave_lds_sync();
-  {
-    T* zr = re + (N2 + 1) * k1;
-    T* zi = im + (N2 + 1) * k1;
+#pragma unroll
+  for (int t = 0; t < I2; ++t) {
+    const int item = lane + 64 * t;
+    const int k1 = item % N1;
+    T* const zr = re_of(item / N1) + (N2 + 1) * k1;
+    T* const zi = zr + LDP;
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) {
-      const cx<T> g = cmulc(yk[n2], stw[k1 * (N2 + 1) + n2]);
+      const cx<T> g = cmulc(yk[t][n2], stw[k1 * (N2 + 1) + n2]);
       zr[n2] = g.re;
       zi[n2] = g.im;
     }
@@ -339,8 +385,12 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   wave_lds_sync();
 
   // second inverse pass: N1-point DFTs over stride N2, natural order out
-  {
-    const int n2 = idx;
+#pragma unroll
+  for (int t = 0; t < I1; ++t) {
+    const int item = lane + 64 * t;
+    const int n2 = item % N2;
+    T* const re = re_of(item / N2);
+    T* const im = re + LDP;
     cx<T> x[N1];
 #pragma unroll
     for (int kk = 0; kk < N1; ++kk) x[kk] = {re[n2 + (N2 + 1) * kk], im[n2 + (N2 + 1) * kk]};
@@ -364,13 +414,9 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
     T o[NC][K];
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
-      Quad<T> qv;
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        o[comp][j] = base[i][comp][j] + coef * s[(i * NC + comp) * LDP + wave_pad(a0 + j)];
-        qv.v[j] = o[comp][j];
-      }
-      buf_store4(qv, ro, qo[i + 3], comp * cbytes);
+      for (int j = 0; j < K; ++j) o[comp][j] = base[i][comp][j] + coef * s[(i * NC + comp) * LDP + pad(a0 + j)];
+      buf_store_n<K>(o[comp], ro, qo[i + 3], comp * cbytes);
     }
     if (want_trace) {
 #pragma unroll
@@ -380,14 +426,22 @@ __global__ void __launch_bounds__(WavePlan::NT, 2) stage_wave_kernel(StageArgs a
   }
   if (want_trace) {
     for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
-    if (lane == 0) a.partials[((long long)b * kRespSlots + a.slot) * a.ntiles + pair] = tr;
+    if (lane == 0) a.partials[((long long)b * kRespSlots + a.slot) * a.ntiles + tile] = tr;
   }
 }
 
 template <typename T>
-hipError_t launch_stage_wave(const StageArgs& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((stage_wave_kernel<T>), dim3(nblocks), dim3(WavePlan::NT), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_stage_wave(int np, const StageArgs& a, int nblocks, hipStream_t s) {
+  switch (np) {
+    case 128:
+      hipLaunchKernelGGL((stage_wave_kernel<T, 128>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
+      return hipGetLastError();
+    case 256:
+      hipLaunchKernelGGL((stage_wave_kernel<T, 256>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
+      return hipGetLastError();
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace qhfpe

@@ -1,6 +1,6 @@
 """Parity of the wave-independent stage variant (tile code 1: one wave per
-pair of q columns; two states, np = 256) with the FP64 oracle and with the
-workgroup variant.
+512/np q columns; two states, np = 128 or 256) with the FP64 oracle and with
+the workgroup variant.
 
 Bars as in test_gpu_parity.py: FP64 relative L2 <= 1e-12 per operator
 application, variants agree to 1e-13 (FP64) / 1e-5 (FP32) after
@@ -38,9 +38,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def model(nq=13, depth=2, coupling=0.3, **kw):
+def model(nq=13, depth=2, coupling=0.3, np_=256, **kw):
     base = inputs.SMALL_ABSORPTION["model"]
-    d = inputs.model_dict(base, n_states=2, nq=nq, np=256, depth=depth, poly=inputs.two_state_surfaces(coupling),
+    d = inputs.model_dict(base, n_states=2, nq=nq, np=np_, depth=depth, poly=inputs.two_state_surfaces(coupling),
                           mu=[[0, 1], [1, 0]])
     d.update(kw)
     return d
@@ -48,7 +48,7 @@ def model(nq=13, depth=2, coupling=0.3, **kw):
 
 def rhs_case(d, precision, seed, phase, smooth=True):
     m = oracle_model(d)
-    W = inputs.random_hierarchy(d["depth"], 2, d["nq"], 256, seed=seed, phase=phase, smooth=smooth)
+    W = inputs.random_hierarchy(d["depth"], 2, d["nq"], d["np"], seed=seed, phase=phase, smooth=smooth)
     P = qhfpe.Propagator(d, batch=1, precision=precision)
     P.set_tile(WAVE)
     P.set_state(torch.from_numpy(W[None]), phase=phase)
@@ -58,40 +58,46 @@ def rhs_case(d, precision, seed, phase, smooth=True):
     return rel(got, O.rhs(m, W))
 
 
-@pytest.mark.parametrize("nq,depth", [(13, 2), (8, 0), (48, 1), (9, 3)])
+@pytest.mark.parametrize("np_", [128, 256])
+@pytest.mark.parametrize("nq,depth", [(13, 2), (8, 0), (48, 1), (9, 3), (6, 1)])
 @pytest.mark.parametrize("phase", [0, 1])
-def test_wave_rhs_parity(nq, depth, phase):
-    """Ragged (odd nq) and edge-only tilings, the terminator at depth 0."""
-    say(f"wave rhs nq={nq} depth={depth} phase={phase}")
-    err = rhs_case(model(nq=nq, depth=depth), "fp64", seed=500 + nq + depth + phase, phase=phase)
+def test_wave_rhs_parity(nq, depth, phase, np_):
+    """Ragged (nq not a multiple of the task width) and edge-only tilings,
+    the terminator at depth 0."""
+    say(f"wave rhs np={np_} nq={nq} depth={depth} phase={phase}")
+    err = rhs_case(model(nq=nq, depth=depth, np_=np_), "fp64", seed=500 + nq + depth + phase + np_, phase=phase)
     assert err < 1e-12, err
 
 
-def test_wave_rhs_parity_rough_and_uncoupled():
+@pytest.mark.parametrize("np_", [128, 256])
+def test_wave_rhs_parity_rough_and_uncoupled(np_):
     """Unsmoothed data (every stencil weight matters) and zero coupling."""
-    say("wave rhs rough / uncoupled")
-    assert rhs_case(model(nq=11, depth=2), "fp64", seed=91, phase=0, smooth=False) < 1e-12
-    assert rhs_case(model(nq=11, depth=2, coupling=0.0), "fp64", seed=92, phase=1) < 1e-12
+    say(f"wave rhs rough / uncoupled np={np_}")
+    assert rhs_case(model(nq=11, depth=2, np_=np_), "fp64", seed=91, phase=0, smooth=False) < 1e-12
+    assert rhs_case(model(nq=11, depth=2, coupling=0.0, np_=np_), "fp64", seed=92, phase=1) < 1e-12
 
 
-def test_wave_rhs_parity_p_zero_inside_a_lane():
-    """A p grid whose sign change falls between the four nodes of one lane
+@pytest.mark.parametrize("np_", [128, 256])
+def test_wave_rhs_parity_p_zero_inside_a_lane(np_):
+    """A p grid whose sign change falls between the nodes of one lane
     (the mirrored upwind stencil for part of a lane)."""
-    say("wave rhs mixed-sign lane")
-    d = model(nq=12, depth=1, p_min=-7.9, p_max=8.1)
+    say(f"wave rhs mixed-sign lane np={np_}")
+    d = model(nq=12, depth=1, np_=np_, p_min=-7.9, p_max=8.1)
     assert rhs_case(d, "fp64", seed=93, phase=0, smooth=False) < 1e-12
 
 
-def test_wave_rhs_parity_fp32():
-    say("wave rhs fp32")
-    assert rhs_case(model(nq=13, depth=2), "fp32", seed=94, phase=0) < 1e-5
+@pytest.mark.parametrize("np_", [128, 256])
+def test_wave_rhs_parity_fp32(np_):
+    say(f"wave rhs fp32 np={np_}")
+    assert rhs_case(model(nq=13, depth=2, np_=np_), "fp32", seed=94, phase=0) < 1e-5
 
 
+@pytest.mark.parametrize("np_", [128, 256])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_wave_agrees_with_workgroup_variant(precision):
+def test_wave_agrees_with_workgroup_variant(precision, np_):
     """Propagation with two members of different baths, traces every 3 steps."""
-    say(f"wave vs workgroup {precision}")
-    d = model(nq=26, depth=3)
+    say(f"wave vs workgroup {precision} np={np_}")
+    d = model(nq=26, depth=3, np_=np_)
     out = {}
     for tile in (4, WAVE):
         P = qhfpe.Propagator(d, batch=2, precision=precision)
@@ -111,7 +117,7 @@ def test_wave_availability():
     P = qhfpe.Propagator(d, batch=1, precision="fp64")
     assert P.autotune(2) in (WAVE, 2, 4)
     P.close()
-    for bad in (inputs.model_dict(d, np=128), inputs.model_dict(
+    for bad in (inputs.model_dict(d, np=64), inputs.model_dict(d, np=192), inputs.model_dict(
             d, n_states=3, poly=inputs.three_state_surfaces(0.3, 0.2), mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])):
         P = qhfpe.Propagator(bad, batch=1, precision="fp64")
         with pytest.raises(qhfpe.QHFPEError):
