@@ -252,7 +252,11 @@ struct qhfpe_handle {
   int cpt = 4;  // stage tile variant (cells per thread along q)
 
   bool wave() const { return cpt == kTileWave; }
-  int tq() const { return wave() ? wave_columns(p.np) : plan_groups(p.np) * cpt; }
+  static int tq_of(int np, int code) { return code == kTileWave ? wave_columns(np) : plan_groups(np) * code; }
+  int tq() const { return tq_of(p.np, cpt); }
+  // the trace partials hold L.max_tiles tiles per member and slot: a variant
+  // with narrower tiles would index past them
+  bool tile_fits(int code) const { return (p.nq + tq_of(p.np, code) - 1) / tq_of(p.np, code) <= L.max_tiles; }
   int ntiles() const { return (p.nq + tq() - 1) / tq(); }
   double dq = 0, dp = 0;
 
@@ -480,7 +484,7 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
 int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
   if (int rc = check_handle(h)) return rc;
   const int c = cells_per_thread == 0 ? tile_default((int)h->L.elem, h->ns, h->p.np) : cells_per_thread;
-  if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c))
+  if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c))
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
   h->cpt = c;
   return QHFPE_OK;
@@ -502,7 +506,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   float best_ms = 1e30f;
   int rc = QHFPE_OK;
   for (int c : candidates) {
-    if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c)) continue;
+    if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c)) continue;
     h->cpt = c;
     StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
     hipError_t e = h->launch(a);  // warm-up
