@@ -36,8 +36,8 @@ def kernel_source_sha() -> str:
 
 
 def read_traffic(precision: str):
-    """HBM bytes per stage launch from the committed rocprofv3 --pmc summary,
-    if it was taken on the current kernel source (else None)."""
+    """HBM bytes per stage pass (all members) from the committed rocprofv3
+    --pmc summary, if it was taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"stage_kernel_256x256_depth8_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -49,7 +49,7 @@ def read_traffic(precision: str):
     if kv.get("kernel_source_sha") != kernel_source_sha():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_stage_pass"])
     except (KeyError, ValueError):
         return None
 
@@ -103,6 +103,8 @@ def main():
                          "columns per thread; 0: autotune before the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="member groups of each step on streams of their own (0 = library default)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--two-d", action="store_true",
                     help="also time the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
@@ -149,6 +151,8 @@ def main():
             tile = args.tile
         else:
             tile = P.autotune(20)
+        P.set_streams(args.groups)
+        groups = P.streams()
         resp = torch.empty((len(zetas), nsteps + 1), dtype=torch.complex128, device=dev)
         spec = [None] * len(zetas)
 
@@ -174,20 +178,23 @@ def main():
         gpu_s = e0.elapsed_time(e1) / 1e3
         cells = (base["depth"] + 1) * base["nq"] * base["np"]
         updates = steps * len(zetas) * nsteps * cells
-        launches = steps * nsteps * 4
+        # a stage pass is one RK4 stage over all members: `groups` launches on
+        # their own streams that overlap, so its duration is the timed GPU time
+        # per pass, not one launch's start-to-end time
+        passes = steps * nsteps * 4
         w = 8 if precision == "fp64" else 4
         nc = base["n_states"] ** 2
         # algorithmic bytes per RK4 step and cell: stage 1 reads y (as v and y) and writes
         # v_a (2 passes); stages 2-4 read v, read y and write (3 passes each)
-        bytes_per_launch = 11 * nc * w * cells * len(zetas) / 4.0
-        launch_s = gpu_s / launches
-        achieved = bytes_per_launch / launch_s / 1e9
+        bytes_per_pass = 11 * nc * w * cells * len(zetas) / 4.0
+        launch_s = gpu_s / passes
+        achieved = bytes_per_pass / launch_s / 1e9
         traffic = read_traffic(precision)
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
-                    avg_launch_us=round(launch_s * 1e6, 3), bytes_per_launch=bytes_per_launch,
-                    tile_variant=tile,
+                    avg_stage_pass_us=round(launch_s * 1e6, 3), bytes_per_stage_pass=bytes_per_pass,
+                    member_groups=groups, tile_variant=tile,
                     kernel_source_sha=kernel_source_sha())
         out = dict(value=updates / wall, wall_s=wall, gpu_s=gpu_s, ms_per_step=1e3 * wall / steps,
                    roofline=roof, resp=resp.cpu().numpy(), spec=[s.cpu().numpy() for s in spec])

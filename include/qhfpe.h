@@ -129,6 +129,23 @@ int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread);
  * changed).  h_chosen (may be NULL) receives the variant.  Synchronous. */
 int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen);
 
+/* Member groups of qhfpe_step (batching of independent propagations, as in
+ * Sec. III's runs over baths and delays).  The members are split into
+ * `groups` contiguous ranges; each range's stage launches go to a stream of
+ * its own, created by the library on first use and destroyed with the handle,
+ * so that the launches of different ranges overlap on the GPU.  qhfpe_step
+ * still runs after earlier work on the handle's stream and before later work
+ * (an event fork and join on that stream).  Results do not depend on the
+ * grouping: every member is computed by the same kernels in the same order.
+ * groups: 1 = one launch per stage for all members; 2..4 = that many ranges
+ * (capped at the batch size); 0 = default (one group per member for batches
+ * of up to 3 members, 2 groups for 4..8 members, else 1).  Only qhfpe_step (and qhfpe_relax through it) uses the groups.
+ * QHFPE_EINVAL if groups is outside [0, 4]. */
+int qhfpe_set_streams(qhfpe_t* h, int32_t groups);
+
+/* Member groups qhfpe_step will use (after capping and the default rule). */
+int qhfpe_get_streams(const qhfpe_t* h, int32_t* groups);
+
 /* Initial state (Sec. III protocol; harmonic thermal Wigner function):
  * W^(0)_00(p, q) = tanh(b)/(pi hbar) exp(-tanh(b) [p^2/(m hbar omega) + m omega q^2/hbar]),
  * b = beta hbar omega/2 with each member's beta, plus d_noise[i][a] (FP64

@@ -250,6 +250,45 @@ struct qhfpe_handle {
   int phase = 0;
   int ns = 0, nc = 0, levels = 0;
   int cpt = 4;  // stage tile variant (cells per thread along q)
+  // Member groups of qhfpe_step: each group's launches go to a stream of its
+  // own, so that one group's next stage fills the GPU while another's launch
+  // drains.  Created on first use, destroyed with the handle.
+  int groups_req = 0;  // 0 = default rule
+  int groups_made = 0;
+  hipStream_t gstream[kMaxGroups] = {};
+  hipEvent_t gfork = nullptr;
+  hipEvent_t gjoin[kMaxGroups] = {};
+
+  ~qhfpe_handle() {
+    for (int g = 0; g < groups_made; ++g) {
+      if (gstream[g]) hipStreamDestroy(gstream[g]);
+      if (gjoin[g]) hipEventDestroy(gjoin[g]);
+    }
+    if (gfork) hipEventDestroy(gfork);
+  }
+
+  // Default for small batches, where one launch per stage leaves most SIMDs
+  // with two or three waves that all load, then all transform, in step: one
+  // group per member up to three members, two groups for 4..8 members; one
+  // group above that.
+  int groups() const {
+    int want = groups_req;
+    if (want == 0) want = p.batch <= 3 ? p.batch : (p.batch <= 8 ? 2 : 1);
+    return std::min(want, p.batch);
+  }
+
+  hipError_t make_groups(int n) {
+    if (!gfork) {
+      hipError_t e = hipEventCreateWithFlags(&gfork, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    for (; groups_made < n; ++groups_made) {
+      hipError_t e = hipStreamCreateWithFlags(&gstream[groups_made], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&gjoin[groups_made], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
 
   bool wave() const { return cpt == kTileWave; }
   static int tq_of(int np, int code) { return code == kTileWave ? wave_columns(np) : plan_groups(np) * code; }
@@ -305,9 +344,7 @@ struct qhfpe_handle {
     a.depth = p.depth;
     a.ntiles = ntiles();
     a.batch = p.batch;
-    const int units = ntiles() * levels * p.batch;  // workgroups, or waves of the wave variant
-    const int blocks = wave() ? (units + kWaveTasksPerBlock - 1) / kWaveTasksPerBlock : units;
-    a.nblocks_padded = (blocks + 7) / 8 * 8;
+    a.nblocks_padded = padded_blocks(p.batch);
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;
@@ -324,16 +361,38 @@ struct qhfpe_handle {
     return a;
   }
 
-  hipError_t launch(const StageArgs& a) const {
+  // grid of a stage launch over `batch` members, rounded up to a multiple of 8
+  int padded_blocks(int batch) const {
+    const int units = ntiles() * levels * batch;  // workgroups, or waves of the wave variant
+    const int blocks = wave() ? (units + kWaveTasksPerBlock - 1) / kWaveTasksPerBlock : units;
+    return (blocks + 7) / 8 * 8;
+  }
+
+  // the same stage restricted to members first .. first + count - 1
+  StageArgs member_slice(StageArgs a, int first, int count) const {
+    const size_t off = (size_t)first * L.member_elems * L.elem;
+    a.v = static_cast<const char*>(a.v) + off;
+    if (a.y) a.y = static_cast<const char*>(a.y) + off;
+    a.out = static_cast<char*>(a.out) + off;
+    a.bath += (long long)kBathStride * first;
+    if (a.partials) a.partials += (long long)first * kRespSlots * a.ntiles;
+    a.batch = count;
+    a.nblocks_padded = padded_blocks(count);
+    return a;
+  }
+
+  hipError_t launch(const StageArgs& a) const { return launch_on(a, stream); }
+
+  hipError_t launch_on(const StageArgs& a, hipStream_t s) const {
     const int nblocks = a.nblocks_padded;
     if (wave())
-      return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(p.np, a, nblocks, stream)
-                                       : launch_stage_wave_f32(p.np, a, nblocks, stream);
+      return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(p.np, a, nblocks, s)
+                                       : launch_stage_wave_f32(p.np, a, nblocks, s);
     if (p.precision == QHFPE_FP64)
-      return ns == 2 ? launch_stage_f64_ns2(p.np, cpt, a, nblocks, stream)
-                     : launch_stage_f64_ns3(p.np, cpt, a, nblocks, stream);
-    return ns == 2 ? launch_stage_f32_ns2(p.np, cpt, a, nblocks, stream)
-                   : launch_stage_f32_ns3(p.np, cpt, a, nblocks, stream);
+      return ns == 2 ? launch_stage_f64_ns2(p.np, cpt, a, nblocks, s)
+                     : launch_stage_f64_ns3(p.np, cpt, a, nblocks, s);
+    return ns == 2 ? launch_stage_f32_ns2(p.np, cpt, a, nblocks, s)
+                   : launch_stage_f32_ns3(p.np, cpt, a, nblocks, s);
   }
 };
 
@@ -353,6 +412,15 @@ int trace_into(qhfpe_t* h, int slot) {
 int finalize(qhfpe_t* h, int nslots, double* resp, long long resp_stride, long long offset) {
   HIP_TRY(launch_finalize(h->p.batch, h->ntiles(), nslots, h->partials(), h->dq * h->dp, h->phase, resp,
                           resp_stride, offset, h->flag(), h->stream));
+  return QHFPE_OK;
+}
+
+// finalize for members first .. first + count - 1 on stream s
+int finalize_members(qhfpe_t* h, int first, int count, int nslots, double* resp, long long resp_stride,
+                     long long offset, hipStream_t s) {
+  HIP_TRY(launch_finalize(count, h->ntiles(), nslots, h->partials() + (long long)first * kRespSlots * h->ntiles(),
+                          h->dq * h->dp, h->phase, resp ? resp + (long long)first * resp_stride : nullptr,
+                          resp_stride, offset, h->flag(), s));
   return QHFPE_OK;
 }
 
@@ -532,6 +600,20 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   return rc;
 }
 
+int qhfpe_set_streams(qhfpe_t* h, int32_t groups) {
+  if (int rc = check_handle(h)) return rc;
+  if (groups < 0 || groups > kMaxGroups) return fail(QHFPE_EINVAL, "groups must be in [0, %d]", kMaxGroups);
+  h->groups_req = groups;
+  return QHFPE_OK;
+}
+
+int qhfpe_get_streams(const qhfpe_t* h, int32_t* groups) {
+  if (int rc = check_handle(h)) return rc;
+  if (!groups) return fail(QHFPE_EINVAL, "groups is NULL");
+  *groups = h->groups();
+  return QHFPE_OK;
+}
+
 int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase) {
   if (int rc = check_handle(h)) return rc;
   if (!phase) return fail(QHFPE_EINVAL, "phase is NULL");
@@ -616,23 +698,67 @@ int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
   StageArgs s2 = h->stage_args(h->va(), h->y(), h->vb(), dt / 3.0);
   StageArgs s3 = h->stage_args(h->vb(), h->y(), h->va(), 0.5 * dt);
   StageArgs s4 = h->stage_args(h->va(), h->y(), h->y(), dt);
-  for (int64_t s = 1; s <= nsteps; ++s) {
-    HIP_TRY(h->launch(s1));
-    HIP_TRY(h->launch(s2));
-    HIP_TRY(h->launch(s3));
-    const bool sample = d_resp && (s % stride == 0);
-    s4.partials = sample ? h->partials() : nullptr;
-    s4.slot = slot;
-    HIP_TRY(h->launch(s4));
-    if (sample && ++slot == kRespSlots) {
-      if (int rc = finalize(h, slot, d_resp, nsamples * 2, base)) return rc;
-      base += slot;
-      slot = 0;
+  // member groups: group g holds members first[g] .. first[g + 1] - 1 and
+  // runs on its own stream between a fork and a join on the handle's stream
+  const int G = nsteps > 0 ? h->groups() : 1;
+  int first[kMaxGroups + 1];
+  for (int g = 0; g <= G; ++g) first[g] = (int)((long long)g * h->p.batch / G);
+  hipStream_t gs[kMaxGroups];
+  StageArgs g1[kMaxGroups], g2[kMaxGroups], g3[kMaxGroups];
+  if (G > 1) {
+    HIP_TRY(h->make_groups(G));
+    HIP_TRY(hipEventRecord(h->gfork, h->stream));
+    for (int g = 0; g < G; ++g) {
+      gs[g] = h->gstream[g];
+      HIP_TRY(hipStreamWaitEvent(gs[g], h->gfork, 0));
+    }
+  } else {
+    gs[0] = h->stream;
+  }
+  for (int g = 0; g < G; ++g) {
+    const int cnt = first[g + 1] - first[g];
+    g1[g] = G > 1 ? h->member_slice(s1, first[g], cnt) : s1;
+    g2[g] = G > 1 ? h->member_slice(s2, first[g], cnt) : s2;
+    g3[g] = G > 1 ? h->member_slice(s3, first[g], cnt) : s3;
+  }
+  auto run = [&]() -> int {
+    for (int64_t s = 1; s <= nsteps; ++s) {
+      const bool sample = d_resp && (s % stride == 0);
+      s4.partials = sample ? h->partials() : nullptr;
+      s4.slot = slot;
+      for (int g = 0; g < G; ++g) {
+        HIP_TRY(h->launch_on(g1[g], gs[g]));
+        HIP_TRY(h->launch_on(g2[g], gs[g]));
+        HIP_TRY(h->launch_on(g3[g], gs[g]));
+        HIP_TRY(h->launch_on(G > 1 ? h->member_slice(s4, first[g], first[g + 1] - first[g]) : s4, gs[g]));
+      }
+      if (sample && ++slot == kRespSlots) {
+        for (int g = 0; g < G; ++g)
+          if (int rc = finalize_members(h, first[g], first[g + 1] - first[g], slot, d_resp, nsamples * 2, base,
+                                        gs[g]))
+            return rc;
+        base += slot;
+        slot = 0;
+      }
+    }
+    if (d_resp && slot > 0) {
+      for (int g = 0; g < G; ++g)
+        if (int rc =
+                finalize_members(h, first[g], first[g + 1] - first[g], slot, d_resp, nsamples * 2, base, gs[g]))
+          return rc;
+    }
+    return QHFPE_OK;
+  };
+  int rc_run = run();
+  if (G > 1) {
+    // join even after an error, so that the handle's stream orders later work
+    for (int g = 0; g < G; ++g) {
+      if (hipEventRecord(h->gjoin[g], gs[g]) != hipSuccess ||
+          hipStreamWaitEvent(h->stream, h->gjoin[g], 0) != hipSuccess)
+        if (rc_run == QHFPE_OK) rc_run = fail(QHFPE_EHIP, "step: joining member groups failed");
     }
   }
-  if (d_resp && slot > 0) {
-    if (int rc = finalize(h, slot, d_resp, nsamples * 2, base)) return rc;
-  }
+  if (rc_run) return rc_run;
   if (!d_resp) {
     if (int rc = trace_into(h, 0)) return rc;
     if (int rc = finalize(h, 1, nullptr, 0, 0)) return rc;

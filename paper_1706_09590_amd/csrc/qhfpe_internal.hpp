@@ -46,6 +46,7 @@ inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns =
 // Tile code of the wave-independent stage variant (stage_wave.hpp): one
 // wave per pair of q columns, two states and np = 256 only.
 constexpr int kTileWave = 1;
+constexpr int kMaxGroups = 4;  // member groups (streams) of qhfpe_step
 constexpr int kWaveTasksPerBlock = 4;  // waves per workgroup of the wave variant
 inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
 // q columns per task of the wave variant (a lane holds np / 64 p nodes)

@@ -164,22 +164,22 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   const T zterm = has_up ? T(0) : zeta;
 
   // ---- local terms, one component at a time ------------------------------
-  // Loads of component c + 1 are issued while component c is computed (two
-  // register slots): the level loads before c's kinetic term, the window
-  // and y before c + 1's level terms.  Double has no registers to spare for
-  // a second slot and computes the components one after the other.
+  // v^(n) at the task columns is the middle of the kinetic window, so it is
+  // loaded once.  Loads of component c + 1 are issued while component c is
+  // computed (two register slots): the window and y after c's kinetic term,
+  // v^(n +- 1) after c's level terms.  Double has no registers to spare for a
+  // second slot; it issues all loads of a component together.
   constexpr bool kPipe = sizeof(T) == 4;
   constexpr int NS_ = kPipe ? 2 : 1;
   T base[C][NC][K];  // y + coef * (all terms except the potential)
-  T lw[NS_][3][C][K];         // level loads: v^(n), v^(n+1), v^(n-1) at the task columns
+  T lw[NS_][2][C][K];         // v^(n+1), v^(n-1) at the task columns
   T kw[NS_][2 * C + 6][K];    // kinetic window q0-3 .. q0+C+2, then y at the task columns
   auto issue_level = [&](int comp, int slot) {
     const unsigned so = comp * cbytes;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-      buf_load_n<K>(rn, qo[i + 3], so, lw[slot][0][i]);
-      buf_load_n<K>(ru, qo[i + 3], so, lw[slot][1][i]);
-      buf_load_n<K>(rd, qo[i + 3], so, lw[slot][2][i]);
+      buf_load_n<K>(ru, qo[i + 3], so, lw[slot][0][i]);
+      buf_load_n<K>(rd, qo[i + 3], so, lw[slot][1][i]);
     }
   };
   auto issue_kinetic = [&](int comp, int slot) {
@@ -190,29 +190,53 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
     for (int i = 0; i < C; ++i) buf_load_n<K>(ry, qo[i + 3], so, kw[slot][C + 6 + i]);
   };
   if (kPipe) {
-    issue_level(0, 0);
     issue_kinetic(0, 0);
+    issue_level(0, 0);
   }
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     const int sl = kPipe ? (comp & 1) : 0;
     if (!kPipe) {
       if (comp > 0) __builtin_amdgcn_sched_barrier(0);
+      issue_kinetic(comp, 0);
       issue_level(comp, 0);
     }
-    // level field and level terms at the lane's nodes of every column
-    T lev[C][K];
+    // kinetic term at the lane's nodes of every column
+    T kin[C][K];
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-      T g[K];
+    for (int i = 0; i < C; ++i)
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const T w0 = lw[sl][0][i][j];
+        T k = T(0);
+#pragma unroll
+        for (int o = 0; o < 7; ++o) k += kc[o] * kw[sl][i + o][j];
+        if (any_mixed && ((p[j] >= T(0)) != pos0)) {
+          // where p = 0 falls inside a lane, its nodes of the other sign
+          // take the mirrored stencil
+          k = T(0);
+#pragma unroll
+          for (int o = 0; o < 7; ++o) k += kcm[o] * kw[sl][i + o][j];
+        }
+        kin[i][j] = kscale[j] * k;
+        asm volatile("" : "+v"(kin[i][j]));
+      }
+    if (kPipe) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (comp + 1 < NC) issue_kinetic(comp + 1, sl ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // level field and level terms, then the base state
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      T g[K], lev[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const T w0 = kw[sl][i + 3][j];
         // field differentiated once along p:
         //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
         // (the absent neighbour levels read as zero; n gamma = 0 at n = 0)
-        g[j] = lw[sl][1][i][j] + (zterm * p[j]) * w0 + (ng * c0) * lw[sl][2][i][j];
-        lev[i][j] = -ng * w0 + (ng * zeta * p[j]) * lw[sl][2][i][j];
+        g[j] = lw[sl][0][i][j] + (zterm * p[j]) * w0 + (ng * c0) * lw[sl][1][i][j];
+        lev[j] = -ng * w0 + (ng * zeta * p[j]) * lw[sl][1][i][j];
         s[(i * NC + comp) * LDP + pad(a0 + j)] = w0;
       }
       // D_p g: nodes a0-2, a0-1 come from the previous lane, a0+K, a0+K+1
@@ -226,39 +250,14 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
       e[K + 3] = lane_next(g[1]);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        lev[i][j] += dpinv * (-e[j + 4] + T(8) * e[j + 3] - T(8) * e[j + 1] + e[j]);
-        // materialised here, so that its operands are not kept live
-        asm volatile("" : "+v"(lev[i][j]));
+        lev[j] += dpinv * (-e[j + 4] + T(8) * e[j + 3] - T(8) * e[j + 1] + e[j]);
+        base[i][comp][j] = kw[sl][C + 6 + i][j] + coef * (kin[i][j] + lev[j]);
+        asm volatile("" : "+v"(base[i][comp][j]));
       }
     }
     if (kPipe) {
       __builtin_amdgcn_sched_barrier(0);
       if (comp + 1 < NC) issue_level(comp + 1, sl ^ 1);
-      __builtin_amdgcn_sched_barrier(0);
-    } else {
-      issue_kinetic(comp, 0);
-    }
-    // kinetic term and the base state
-#pragma unroll
-    for (int i = 0; i < C; ++i)
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        T kin = T(0);
-#pragma unroll
-        for (int o = 0; o < 7; ++o) kin += kc[o] * kw[sl][i + o][j];
-        if (any_mixed && ((p[j] >= T(0)) != pos0)) {
-          // where p = 0 falls inside a lane, its nodes of the other sign
-          // take the mirrored stencil
-          kin = T(0);
-#pragma unroll
-          for (int o = 0; o < 7; ++o) kin += kcm[o] * kw[sl][i + o][j];
-        }
-        base[i][comp][j] = kw[sl][C + 6 + i][j] + coef * (kscale[j] * kin + lev[i][j]);
-        asm volatile("" : "+v"(base[i][comp][j]));
-      }
-    if (kPipe) {
-      __builtin_amdgcn_sched_barrier(0);
-      if (comp + 1 < NC) issue_kinetic(comp + 1, sl ^ 1);
       __builtin_amdgcn_sched_barrier(0);
     }
   }

@@ -72,6 +72,8 @@ def lib():
         "qhfpe_set_member_bath": ([_vp, _c_i32, _c_dbl, _c_dbl, _c_dbl], _c_int),
         "qhfpe_set_tile": ([_vp, _c_i32], _c_int),
         "qhfpe_autotune": ([_vp, _c_i32, ctypes.POINTER(_c_i32)], _c_int),
+        "qhfpe_set_streams": ([_vp, _c_i32], _c_int),
+        "qhfpe_get_streams": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
         "qhfpe_apply_dipole": ([_vp, _c_i32], _c_int),
         "qhfpe_step": ([_vp, _c_i64, _c_i32, _vp], _c_int),
@@ -200,6 +202,16 @@ class Propagator:
 
     def set_tile(self, cells_per_thread: int):
         _check(lib().qhfpe_set_tile(self.handle, int(cells_per_thread)))
+
+    def set_streams(self, groups: int):
+        """Member groups of step(): 1 = one launch per stage, 2..4 = that many
+        member ranges on streams of their own, 0 = default."""
+        _check(lib().qhfpe_set_streams(self.handle, int(groups)))
+
+    def streams(self) -> int:
+        g = ctypes.c_int32(0)
+        _check(lib().qhfpe_get_streams(self.handle, ctypes.byref(g)))
+        return int(g.value)
 
     def autotune(self, reps: int = 20) -> int:
         v = _c_i32(0)

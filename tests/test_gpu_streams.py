@@ -1,0 +1,120 @@
+"""Member groups of qhfpe_step (qhfpe_set_streams): every grouping gives the
+same result, bit for bit, because every member is computed by the same
+kernels in the same order; the grouping only decides which stream a
+member's launches go to.  One grouping is also checked against the FP64
+oracle, so that the sliced launches (member offsets of the state, the bath
+constants and the trace partials) are pinned to the definition and not only
+to each other.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import oracle_model
+from oracle import qhfpe_oracle as O
+from paper_1706_09590_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1706_09590_amd import qhfpe  # noqa: E402
+
+BATHS = [(1.0, 1.0, 1.0), (0.1, 1.0, 1.0), (0.5, 0.8, 0.7), (0.8, 1.2, 1.5), (0.3, 0.9, 2.0)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def model(nq=26, np_=256, depth=3, **kw):
+    # the production step (dt = 0.002) keeps RK4 stable at np = 256
+    base = inputs.SMALL_ABSORPTION["model"]
+    return inputs.model_dict(base, n_states=2, nq=nq, np=np_, depth=depth, poly=inputs.two_state_surfaces(0.3),
+                             mu=[[0, 1], [1, 0]], dt=0.002, **kw)
+
+
+def run(d, batch, precision, tile, groups, nsteps, stride, stream=None):
+    P = qhfpe.Propagator(d, batch=batch, precision=precision, stream=stream)
+    try:
+        for m in range(batch):
+            P.set_member_bath(m, *BATHS[m % len(BATHS)])
+        P.set_tile(tile)
+        P.set_streams(groups)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        tr = P.step(nsteps, stride).cpu().numpy()
+        st = P.get_state().cpu().numpy()
+        # a second call continues from the state the first one left
+        tr2 = P.step(2 * stride, stride).cpu().numpy()
+        return tr, st, tr2
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("precision,tile", [("fp64", 1), ("fp32", 1), ("fp64", 4), ("fp32", 4)])
+def test_groupings_agree_bitwise(precision, tile):
+    """Three members split 1 | 2 and 1 | 1 | 1; 300 samples, more than the
+    256 buffered between finalisations."""
+    say(f"groupings {precision} tile={tile}")
+    d = model()
+    ref = run(d, 3, precision, tile, 1, 300, 1)
+    for g in (2, 3, 4):
+        got = run(d, 3, precision, tile, g, 300, 1)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (g, np.max(np.abs(a - b)))
+
+
+def test_grouping_on_a_user_stream():
+    """The fork and join order the groups after earlier work and before later
+    work on the handle's own (non-default) stream."""
+    say("groupings on a user stream")
+    d = model(nq=20, np_=128, depth=2)
+    s = torch.cuda.Stream()
+    ref = run(d, 5, "fp64", 1, 1, 40, 4)
+    with torch.cuda.stream(s):
+        got = run(d, 5, "fp64", 1, 3, 40, 4, stream=s)
+    s.synchronize()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+def test_grouped_step_against_oracle():
+    """Two groups of a three-member FP64 batch, ten RK4 steps, against the
+    oracle's RK4 of every member with its own bath (traces every 5 steps)."""
+    say("grouped step vs oracle")
+    d = model(nq=16, np_=128, depth=2)
+    nsteps, stride = 10, 5
+    P = qhfpe.Propagator(d, batch=3, precision="fp64")
+    for m in range(3):
+        P.set_member_bath(m, *BATHS[m])
+    P.set_tile(1)
+    P.set_streams(2)
+    P.init_thermal(1.0)
+    P.apply_dipole()
+    tr = P.step(nsteps, stride).cpu().numpy()
+    st = P.get_state().cpu().numpy()
+    P.close()
+    for m in range(3):
+        z, g, b = BATHS[m]
+        om = oracle_model(inputs.model_dict(d, zeta=z, gamma=g, beta=b))
+        W, ref = O.propagate(om, O.dipole_commutator(om, O.thermal_initial_state(om, 1.0)), nsteps, stride)
+        assert np.linalg.norm(tr[m] - ref) <= 1e-11 * np.linalg.norm(ref), m
+        assert np.linalg.norm(st[m] - W) <= 1e-11 * np.linalg.norm(W), m
+
+
+def test_default_rule_and_limits():
+    d = model(nq=12, np_=128, depth=1)
+    for batch, want in ((1, 1), (2, 2), (3, 3), (4, 2), (8, 2), (9, 1)):
+        P = qhfpe.Propagator(d, batch=batch, precision="fp64")
+        assert P.streams() == want, batch
+        P.set_streams(4)
+        assert P.streams() == min(4, batch)
+        for bad in (-1, 5):
+            with pytest.raises(qhfpe.QHFPEError):
+                P.set_streams(bad)
+        P.close()
