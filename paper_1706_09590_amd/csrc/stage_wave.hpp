@@ -165,15 +165,17 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
 
   // ---- local terms, one component at a time ------------------------------
   // v^(n) at the task columns is the middle of the kinetic window, so it is
-  // loaded once.  Loads of component c + 1 are issued while component c is
-  // computed (two register slots): the window and y after c's kinetic term,
-  // v^(n +- 1) after c's level terms.  Double has no registers to spare for a
-  // second slot; it issues all loads of a component together.
+  // loaded once.  In FP32 the loads of component c + 1 are issued while
+  // component c is computed, into second register slots: the window and y
+  // after c's kinetic term, v^(n +- 1) after c's level terms.  Double has no
+  // registers for a second window; it issues all loads of component c + 1
+  // once component c is done.
   constexpr bool kPipe = sizeof(T) == 4;
-  constexpr int NS_ = kPipe ? 2 : 1;
+  constexpr int NSW = kPipe ? 2 : 1;  // window slots
   T base[C][NC][K];  // y + coef * (all terms except the potential)
-  T lw[NS_][2][C][K];         // v^(n+1), v^(n-1) at the task columns
-  T kw[NS_][2 * C + 6][K];    // kinetic window q0-3 .. q0+C+2, then y at the task columns
+  T lw[2][2][C][K];     // v^(n+1), v^(n-1) at the task columns
+  T ky[2][C][K];        // y at the task columns
+  T kw[NSW][C + 6][K];  // kinetic window q0-3 .. q0+C+2
   auto issue_level = [&](int comp, int slot) {
     const unsigned so = comp * cbytes;
 #pragma unroll
@@ -182,25 +184,29 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
       buf_load_n<K>(rd, qo[i + 3], so, lw[slot][1][i]);
     }
   };
-  auto issue_kinetic = [&](int comp, int slot) {
+  auto issue_window = [&](int comp, int slot) {
     const unsigned so = comp * cbytes;
 #pragma unroll
     for (int t = 0; t < C + 6; ++t) buf_load_n<K>(rn, qo[t], so, kw[slot][t]);
-#pragma unroll
-    for (int i = 0; i < C; ++i) buf_load_n<K>(ry, qo[i + 3], so, kw[slot][C + 6 + i]);
   };
-  if (kPipe) {
-    issue_kinetic(0, 0);
-    issue_level(0, 0);
-  }
+  auto issue_y = [&](int comp, int slot) {
+    const unsigned so = comp * cbytes;
+#pragma unroll
+    for (int i = 0; i < C; ++i) buf_load_n<K>(ry, qo[i + 3], so, ky[slot][i]);
+  };
+  // constant diabatic coupling -(i/hbar) [Delta, W] (pointwise in p): with
+  // d = Delta_01 / hbar it adds -2 d Im W01 to W00, +2 d Im W01 to W11, 0 to
+  // Re W01 and d (W00 - W11) to Im W01; it is applied with the last
+  // component, reading W00 and W11 back from this lane's own LDS entries
+  const bool has_coup = a.coup[0][1] != 0.0;
+  const T dcoef = T(a.coef * a.coup[0][1]);
+  issue_window(0, 0);
+  issue_y(0, 0);
+  issue_level(0, 0);
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
-    const int sl = kPipe ? (comp & 1) : 0;
-    if (!kPipe) {
-      if (comp > 0) __builtin_amdgcn_sched_barrier(0);
-      issue_kinetic(comp, 0);
-      issue_level(comp, 0);
-    }
+    const int ws = kPipe ? (comp & 1) : 0;
+    const int ls = comp & 1;
     // kinetic term at the lane's nodes of every column
     T kin[C][K];
 #pragma unroll
@@ -209,34 +215,35 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
       for (int j = 0; j < K; ++j) {
         T k = T(0);
 #pragma unroll
-        for (int o = 0; o < 7; ++o) k += kc[o] * kw[sl][i + o][j];
+        for (int o = 0; o < 7; ++o) k += kc[o] * kw[ws][i + o][j];
         if (any_mixed && ((p[j] >= T(0)) != pos0)) {
           // where p = 0 falls inside a lane, its nodes of the other sign
           // take the mirrored stencil
           k = T(0);
 #pragma unroll
-          for (int o = 0; o < 7; ++o) k += kcm[o] * kw[sl][i + o][j];
+          for (int o = 0; o < 7; ++o) k += kcm[o] * kw[ws][i + o][j];
         }
         kin[i][j] = kscale[j] * k;
         asm volatile("" : "+v"(kin[i][j]));
       }
-    if (kPipe) {
-      __builtin_amdgcn_sched_barrier(0);
-      if (comp + 1 < NC) issue_kinetic(comp + 1, sl ^ 1);
-      __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kPipe && comp + 1 < NC) {
+      issue_window(comp + 1, ws ^ 1);
+      issue_y(comp + 1, ls ^ 1);
     }
+    __builtin_amdgcn_sched_barrier(0);
     // level field and level terms, then the base state
 #pragma unroll
     for (int i = 0; i < C; ++i) {
       T g[K], lev[K];
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const T w0 = kw[sl][i + 3][j];
+        const T w0 = kw[ws][i + 3][j];
         // field differentiated once along p:
         //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
         // (the absent neighbour levels read as zero; n gamma = 0 at n = 0)
-        g[j] = lw[sl][0][i][j] + (zterm * p[j]) * w0 + (ng * c0) * lw[sl][1][i][j];
-        lev[j] = -ng * w0 + (ng * zeta * p[j]) * lw[sl][1][i][j];
+        g[j] = lw[ls][0][i][j] + (zterm * p[j]) * w0 + (ng * c0) * lw[ls][1][i][j];
+        lev[j] = -ng * w0 + (ng * zeta * p[j]) * lw[ls][1][i][j];
         s[(i * NC + comp) * LDP + pad(a0 + j)] = w0;
       }
       // D_p g: nodes a0-2, a0-1 come from the previous lane, a0+K, a0+K+1
@@ -251,34 +258,30 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         lev[j] += dpinv * (-e[j + 4] + T(8) * e[j + 3] - T(8) * e[j + 1] + e[j]);
-        base[i][comp][j] = kw[sl][C + 6 + i][j] + coef * (kin[i][j] + lev[j]);
+        base[i][comp][j] = ky[ls][i][j] + coef * (kin[i][j] + lev[j]);
+        if (comp == NC - 1 && has_coup) {
+          const T w3 = kw[ws][i + 3][j];  // Im W01
+          const T h00 = s[(i * NC + 0) * LDP + pad(a0 + j)], h11 = s[(i * NC + 1) * LDP + pad(a0 + j)];
+          base[i][0][j] -= T(2) * dcoef * w3;
+          base[i][1][j] += T(2) * dcoef * w3;
+          base[i][3][j] += dcoef * (h00 - h11);
+        }
         asm volatile("" : "+v"(base[i][comp][j]));
       }
     }
-    if (kPipe) {
-      __builtin_amdgcn_sched_barrier(0);
-      if (comp + 1 < NC) issue_level(comp + 1, sl ^ 1);
-      __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (comp + 1 < NC) {
+      if (kPipe) {
+        issue_level(comp + 1, ls ^ 1);
+      } else {
+        issue_window(comp + 1, 0);
+        issue_y(comp + 1, ls ^ 1);
+        issue_level(comp + 1, ls ^ 1);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
   wave_lds_sync();
-
-  // constant diabatic couplings: -(i/hbar) [Delta, W], pointwise in p (read
-  // back from LDS: every lane reads only what it wrote)
-  if (a.coup[0][1] != 0.0) {
-    T coup[2][2] = {{T(0), T(a.coup[0][1])}, {T(a.coup[1][0]), T(0)}};
-#pragma unroll
-    for (int i = 0; i < C; ++i)
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        T h[NC], cm[NC];
-#pragma unroll
-        for (int comp = 0; comp < NC; ++comp) h[comp] = s[(i * NC + comp) * LDP + pad(a0 + j)];
-        commutator_mi<2, T>(coup, h, cm);
-#pragma unroll
-        for (int comp = 0; comp < NC; ++comp) base[i][comp][j] += coef * cm[comp];
-      }
-  }
 #pragma unroll
   for (int i = 0; i < C; ++i)
 #pragma unroll
