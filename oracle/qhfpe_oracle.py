@@ -51,6 +51,10 @@ class Model:
 
     ``poly[j, l, k]`` is the coefficient of x^k in U_jl(x)  (k = 0..4), a real
     symmetric matrix of polynomials (Sec. II, Eq. system-Hamiltonian).
+    ``potential_fn``, if given, replaces the polynomials: it maps an array x
+    to U(x) of shape (ns, ns) + x.shape (real symmetric in j, l), e.g. the
+    displaced Morse surfaces and Gaussian coupling of Sec. III
+    (``paper_surfaces``).
     ``mu[j, l]`` is the real symmetric Condon dipole matrix (Sec. III).
     """
 
@@ -72,6 +76,7 @@ class Model:
     hbar: float = 1.0
     low_temp_correction: bool = True
     clamp: bool = True              # reading: U(q +- r/2) clamped to the q-grid
+    potential_fn: object = None
 
     def __post_init__(self):
         self.poly = np.asarray(self.poly, dtype=np.float64)
@@ -150,6 +155,8 @@ def bath_constants(m: Model):
 def potential(m: Model, x: np.ndarray) -> np.ndarray:
     """U_jl(x) for every state pair: array (ns, ns, *x.shape)."""
     x = np.asarray(x, dtype=np.float64)
+    if m.potential_fn is not None:
+        return np.asarray(m.potential_fn(x), dtype=np.float64)
     ns = m.n_states
     out = np.zeros((ns, ns) + x.shape)
     for k in range(m.poly.shape[2]):
@@ -202,6 +209,31 @@ def moyal_term(m: Model, w: np.ndarray, tables=None) -> np.ndarray:
              - np.einsum('jlim,lkim->jkim', rho, um))
     sigma *= -1j / m.hbar
     return np.fft.fft(sigma, axis=-1) / m.np_
+
+
+def paper_surfaces(D0, D1, a0, a1, q0, q1, dE, dV, qs, sigma):
+    """Two-state diabatic surfaces of Sec. III in the dimensionless coordinate
+    q-bar: displaced Morse diagonals and a Gaussian coupling,
+
+        U_00 = D0 (1 - exp(-a0 (q - q0)))^2
+        U_11 = D1 (1 - exp(-a1 (q - q1)))^2 + dE
+        U_01 = U_10 = dV exp(-(q - qs)^2 / (2 sigma^2)).
+
+    Reading: the printed exponent has the opposite sign and no 1/omega_0 in
+    the width; the form above with a_j = omega_j / sqrt(2 D_j omega_0) gives
+    the harmonic frequency omega_j at each minimum and reproduces the printed
+    resonance frequencies nu_0 and nu_1 (see the oracle pins).
+    Returns a function x -> U(x) of shape (2, 2) + x.shape."""
+
+    def U(x):
+        x = np.asarray(x, dtype=np.float64)
+        out = np.empty((2, 2) + x.shape)
+        out[0, 0] = D0 * (1.0 - np.exp(-a0 * (x - q0))) ** 2
+        out[1, 1] = D1 * (1.0 - np.exp(-a1 * (x - q1))) ** 2 + dE
+        out[0, 1] = out[1, 0] = dV * np.exp(-(x - qs) ** 2 / (2.0 * sigma ** 2))
+        return out
+
+    return U
 
 
 # ---------------------------------------------------------------------------
