@@ -112,6 +112,41 @@ int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
  * applies.  Synchronous. */
 int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta);
 
+/* Potential surfaces from a host function instead of params.poly (Sec. II,
+ * Eq. (system-Hamiltonian); the model of Sec. III has displaced Morse
+ * diagonals and a Gaussian coupling, see qhfpe_morse_gauss_potential).
+ * fn(j, l, x, ctx) must return U_jl(x) (same units as params.poly) for
+ * 0 <= j <= l < n_states; U_lj = U_jl is implied.  The library calls fn on
+ * the host, during this call only, at every point the r-space multipliers
+ * of Eq. (quantum-liouvillian) need: q_i +- r_m / 2 clamped to the q grid,
+ * with the Nyquist column averaged as for polynomial surfaces, and
+ * replaces the multipliers of the handle.  fn and ctx are not kept.
+ * If every off-diagonal U_jl takes one and the same value at all those
+ * points, the coupling is applied pointwise as for a constant polynomial;
+ * otherwise it is q-dependent and enters the r-space multiply (mixing the
+ * diagonal and coherence blocks), which only the wave variant implements
+ * (two states, np = 128 or 256): the handle switches to that variant, and
+ * qhfpe_set_tile with a workgroup variant fails until a potential with
+ * constant couplings is set again.  Synchronous.
+ * Errors: QHFPE_EINVAL (fn NULL, a non-finite value), QHFPE_EUNSUPPORTED
+ * (q-dependent coupling with three states or with np other than 128, 256);
+ * on error the handle keeps its previous surfaces. */
+typedef double (*qhfpe_potential_fn)(int32_t j, int32_t l, double x, void* ctx);
+int qhfpe_set_potential(qhfpe_t* h, qhfpe_potential_fn fn, void* ctx);
+
+/* The two-state surfaces of Sec. III in the dimensionless coordinate:
+ *   U_00 = D0 (1 - exp(-a0 (x - q0)))^2
+ *   U_11 = D1 (1 - exp(-a1 (x - q1)))^2 + dE
+ *   U_01 = dV exp(-(x - qs)^2 / (2 sigma^2)).
+ * (The printed exponent is read with the sign and width a_j =
+ * omega_j / sqrt(2 D_j omega_0) that reproduce the printed resonance
+ * frequencies.)  A qhfpe_potential_fn: ctx points to a qhfpe_morse_gauss;
+ * j or l outside {0, 1} returns NaN. */
+typedef struct qhfpe_morse_gauss {
+  double D0, D1, a0, a1, q0, q1, dE, dV, qs, sigma;
+} qhfpe_morse_gauss;
+double qhfpe_morse_gauss_potential(int32_t j, int32_t l, double x, void* ctx);
+
 /* Tile variant of the fused RK stage.  2, 4, 8: each thread of a stage
  * workgroup owns cells_per_thread consecutive q columns (2, 4 or 8 for FP32
  * two-state; 2 or 4 for FP64 two-state and FP32 three-state; 2 for FP64

@@ -125,7 +125,7 @@ Layout make_layout(const qhfpe_params* p) {
   L.off_gtab = off;
   off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
   L.off_mtab = off;
-  if (wave_supported(ns, p->np)) off += align_up((size_t)3 * L.comp_elems * L.elem);
+  if (wave_supported(ns, p->np)) off += align_up((size_t)kWaveTables * L.comp_elems * L.elem);
   L.off_bath = off;
   off += align_up((size_t)p->batch * kBathStride * sizeof(double));
   L.off_psym = off;
@@ -159,8 +159,28 @@ double poly_value(const double* c, double x) {
 
 // r-space multipliers of the potential term at (q_i, r_m), with the argument
 // q +- r/2 clamped to the q-grid and the Nyquist column averaged over +-r.
-void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<double>& dtab,
-                       std::vector<double>& gtab) {
+// Surfaces U_jl(x), j <= l: the params' polynomials or a host function.
+struct Surfaces {
+  const qhfpe_params* p = nullptr;
+  qhfpe_potential_fn fn = nullptr;
+  void* ctx = nullptr;
+  double operator()(int j, int l, double x) const {
+    if (fn) return fn(j, l, x, ctx);
+    return poly_value(p->poly[j][l], x);
+  }
+};
+
+// r-space multipliers at (q_i, r_m) for every table the kernels use:
+//   dtab[j] = (U_jj(q + r/2) - U_jj(q - r/2)) / (2 hbar np)
+//   gtab[pair j<k] = (U_jj(q + r/2) - U_kk(q - r/2)) / (hbar np)
+//   ctab[0], ctab[1] = U_01(q + r/2) / (hbar np), U_01(q - r/2) / (hbar np)  (two states)
+// Arguments are clamped to the q grid; at the Nyquist column both arguments
+// take the average of the two values.  Returns false if a value is not
+// finite; *coup_const tells whether every off-diagonal U_jl had one value
+// (then coup[j][l] holds it divided by hbar).
+bool multiplier_tables(const qhfpe_params& p, const Surfaces& U, double dq, double dp, std::vector<double>& dtab,
+                       std::vector<double>& gtab, std::vector<double>& ctab, bool* coup_const,
+                       double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES]) {
   const int ns = p.n_states, nq = p.nq, np = p.np;
   const double dr = 2.0 * M_PI * p.hbar / (np * dp);
   const double qlo = p.q_min, qhi = p.q_min + (nq - 1) * dq;
@@ -168,42 +188,62 @@ void multiplier_tables(const qhfpe_params& p, double dq, double dp, std::vector<
   const size_t plane = (size_t)nq * np;
   dtab.assign((size_t)ns * plane, 0.0);
   gtab.assign((size_t)(ns * (ns - 1) / 2) * plane, 0.0);
+  ctab.assign(ns == 2 ? 2 * plane : 0, 0.0);
+  double first[QHFPE_MAX_STATES][QHFPE_MAX_STATES] = {};
+  bool seen = false, same = true, finite = true;
   for (int i = 0; i < nq; ++i) {
     const double q = p.q_min + i * dq;
     for (int m = 0; m < np; ++m) {
       const int mh = (m <= np / 2) ? m : m - np;
       const double xp = clampq(q + 0.5 * mh * dr), xm = clampq(q - 0.5 * mh * dr);
       const bool nyq = (m == np / 2);
-      double up[QHFPE_MAX_STATES], um[QHFPE_MAX_STATES];
-      for (int j = 0; j < ns; ++j) {
-        up[j] = poly_value(p.poly[j][j], xp);
-        um[j] = poly_value(p.poly[j][j], xm);
-        if (nyq) up[j] = um[j] = 0.5 * (up[j] + um[j]);
-        dtab[j * plane + (size_t)i * np + m] = (up[j] - um[j]) / (2.0 * p.hbar * np);
-      }
+      double up[QHFPE_MAX_STATES][QHFPE_MAX_STATES], um[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
+      for (int j = 0; j < ns; ++j)
+        for (int l = j; l < ns; ++l) {
+          up[j][l] = U(j, l, xp);
+          um[j][l] = U(j, l, xm);
+          finite = finite && std::isfinite(up[j][l]) && std::isfinite(um[j][l]);
+          if (nyq) up[j][l] = um[j][l] = 0.5 * (up[j][l] + um[j][l]);
+          if (l > j) {
+            if (!seen) first[j][l] = up[j][l];
+            same = same && up[j][l] == first[j][l] && um[j][l] == first[j][l];
+          }
+        }
+      seen = true;
+      const size_t at = (size_t)i * np + m;
+      for (int j = 0; j < ns; ++j) dtab[j * plane + at] = (up[j][j] - um[j][j]) / (2.0 * p.hbar * np);
       int pr = 0;
       for (int j = 0; j < ns; ++j)
-        for (int k = j + 1; k < ns; ++k, ++pr)
-          gtab[pr * plane + (size_t)i * np + m] = (up[j] - um[k]) / (p.hbar * np);
+        for (int k = j + 1; k < ns; ++k, ++pr) gtab[pr * plane + at] = (up[j][j] - um[k][k]) / (p.hbar * np);
+      if (ns == 2) {
+        ctab[at] = up[0][1] / (p.hbar * np);
+        ctab[plane + at] = um[0][1] / (p.hbar * np);
+      }
     }
   }
+  *coup_const = same;
+  for (int j = 0; j < ns; ++j)
+    for (int l = 0; l < ns; ++l)
+      coup[j][l] = (j == l || !same) ? 0.0 : first[std::min(j, l)][std::max(j, l)] / p.hbar;
+  return finite;
 }
 
 // The multiplier tables of the wave variant in one array, each q row
 // permuted so that the n2 values m = k1 + n1 k2 (k2 = 0..n2-1) of row k1
-// are contiguous; the coupling table is stored halved (the kernel treats it as
-// a pair of equal diagonal multipliers).
+// are contiguous: dtab 0, dtab 1, the coherence table halved (the kernel
+// treats it as a pair of equal diagonal multipliers), U_01(q + r/2) and
+// U_01(q - r/2) (used only for a q-dependent coupling).
 void wave_tables(const qhfpe_params& p, int n1, int n2, const std::vector<double>& dtab,
-                 const std::vector<double>& gtab, std::vector<double>& mtab) {
+                 const std::vector<double>& gtab, const std::vector<double>& ctab, std::vector<double>& mtab) {
   const int nq = p.nq, np = p.np;
   const size_t plane = (size_t)nq * np;
-  mtab.assign(3 * plane, 0.0);
-  for (int t = 0; t < 3; ++t)
+  mtab.assign(kWaveTables * plane, 0.0);
+  for (int t = 0; t < kWaveTables; ++t)
     for (int i = 0; i < nq; ++i)
       for (int k1 = 0; k1 < n1; ++k1)
         for (int k2 = 0; k2 < n2; ++k2) {
           const size_t src = (size_t)i * np + k1 + n1 * k2;
-          const double v = (t < 2) ? dtab[t * plane + src] : 0.5 * gtab[src];
+          const double v = (t < 2) ? dtab[t * plane + src] : (t == 2 ? 0.5 * gtab[src] : ctab[(t - 3) * plane + src]);
           mtab[t * plane + (size_t)i * np + (size_t)k1 * n2 + k2] = v;
         }
 }
@@ -250,6 +290,10 @@ struct qhfpe_handle {
   int phase = 0;
   int ns = 0, nc = 0, levels = 0;
   int cpt = 4;  // stage tile variant (cells per thread along q)
+  // off-diagonal couplings: constant (coup, applied pointwise) or
+  // q-dependent (qcoup: the r-space multiply of the wave variant)
+  double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES] = {};
+  int qcoup = 0;
   // Member groups of qhfpe_step: each group's launches go to a stream of its
   // own, so that one group's next stage fills the GPU while another's launch
   // drains.  Created on first use, destroyed with the handle.
@@ -283,9 +327,16 @@ struct qhfpe_handle {
       if (e != hipSuccess) return e;
     }
     for (; groups_made < n; ++groups_made) {
-      hipError_t e = hipStreamCreateWithFlags(&gstream[groups_made], hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&gjoin[groups_made], hipEventDisableTiming);
-      if (e != hipSuccess) return e;
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        if (st) hipStreamDestroy(st);
+        return e;
+      }
+      gstream[groups_made] = st;
+      gjoin[groups_made] = ev;
     }
     return hipSuccess;
   }
@@ -337,6 +388,7 @@ struct qhfpe_handle {
     a.dtab = dtab();
     a.gtab = gtab();
     a.mtab = wave_supported(ns, p.np) ? mtab() : nullptr;
+    a.qcoup = qcoup;
     a.bath = bath();
     a.psym = psym();
     a.slot = 0;
@@ -355,7 +407,7 @@ struct qhfpe_handle {
     a.inv_mass = 1.0 / p.mass;
     for (int j = 0; j < ns; ++j)
       for (int l = 0; l < ns; ++l) {
-        a.coup[j][l] = (j == l) ? 0.0 : p.poly[j][l][0] / p.hbar;
+        a.coup[j][l] = coup[j][l];
         a.mu[j][l] = p.mu[j][l];
       }
     return a;
@@ -446,6 +498,41 @@ int norms(qhfpe_t* h, const void* buf, std::vector<double>& out) {
   return QHFPE_OK;
 }
 
+// Multiplier tables from the surfaces U, uploaded to the handle (computed in
+// FP64 and rounded once to the state precision).  On return with an error
+// the handle's tables and coupling mode are unchanged.
+int install_surfaces(qhfpe_t* h, const Surfaces& U) {
+  std::vector<double> dt, gt, ct, mt;
+  bool coup_const = true;
+  double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
+  if (!multiplier_tables(h->p, U, h->dq, h->dp, dt, gt, ct, &coup_const, coup))
+    return fail(QHFPE_EINVAL, "the potential has a non-finite value on the grid");
+  const bool wave_ok = wave_supported(h->ns, h->p.np);
+  if (!coup_const && !wave_ok)
+    return fail(QHFPE_EUNSUPPORTED, "q-dependent couplings need two states and np = 128 or 256");
+  if (wave_ok) wave_tables(h->p, h->L.n1, h->L.n2, dt, gt, ct, mt);
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const std::vector<double>& src) {
+    if (e != hipSuccess || src.empty()) return;
+    if (h->p.precision == QHFPE_FP64) {
+      e = hipMemcpyAsync(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    } else {
+      std::vector<float> f = convert<float>(src);
+      e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host vectors are temporaries
+  };
+  up(h->dtab(), dt);
+  up(h->gtab(), gt);
+  up(h->mtab(), mt);
+  if (e != hipSuccess) return fail(QHFPE_EHIP, "uploading the potential tables: %s", hipGetErrorString(e));
+  for (int j = 0; j < QHFPE_MAX_STATES; ++j)
+    for (int l = 0; l < QHFPE_MAX_STATES; ++l) h->coup[j][l] = (j < h->ns && l < h->ns) ? coup[j][l] : 0.0;
+  h->qcoup = coup_const ? 0 : 1;
+  if (h->qcoup) h->cpt = kTileWave;
+  return QHFPE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -482,12 +569,9 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
   // setup tables, computed in FP64 and rounded once to the state precision
-  std::vector<double> tw, dt, gt, sym;
+  std::vector<double> tw, sym;
   twiddle_table(params->np, L.n1, L.n2, tw);
   stencil_symbols(params->np, h->dp, sym);
-  multiplier_tables(*params, h->dq, h->dp, dt, gt);
-  std::vector<double> mt;
-  if (wave_supported(params->n_states, params->np)) wave_tables(*params, L.n1, L.n2, dt, gt, mt);
   std::vector<double> bath((size_t)params->batch * kBathStride);
   double bc[kBathStride];
   bath_constants(*params, params->zeta, params->gamma, params->beta, bc);
@@ -505,9 +589,6 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
     }
   };
   up(h->twiddle(), tw);
-  up(h->dtab(), dt);
-  up(h->gtab(), gt);
-  up(h->mtab(), mt);
   up(h->psym(), sym);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bath(), bath.data(), bath.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
@@ -518,8 +599,39 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
     delete h;
     return fail(QHFPE_EHIP, "create: %s", hipGetErrorString(e));
   }
+  Surfaces poly;
+  poly.p = &h->p;
+  if (int rc = install_surfaces(h, poly)) {
+    delete h;
+    return rc;
+  }
   *out = h;
   return QHFPE_OK;
+}
+
+int qhfpe_set_potential(qhfpe_t* h, qhfpe_potential_fn fn, void* ctx) {
+  if (int rc = check_handle(h)) return rc;
+  if (!fn) return fail(QHFPE_EINVAL, "fn is NULL");
+  Surfaces U;
+  U.p = &h->p;
+  U.fn = fn;
+  U.ctx = ctx;
+  return install_surfaces(h, U);
+}
+
+double qhfpe_morse_gauss_potential(int32_t j, int32_t l, double x, void* ctx) {
+  const qhfpe_morse_gauss* c = static_cast<const qhfpe_morse_gauss*>(ctx);
+  if (!c || j < 0 || l < 0 || j > 1 || l > 1) return std::nan("");
+  if (j == 0 && l == 0) {
+    const double e = 1.0 - std::exp(-c->a0 * (x - c->q0));
+    return c->D0 * e * e;
+  }
+  if (j == 1 && l == 1) {
+    const double e = 1.0 - std::exp(-c->a1 * (x - c->q1));
+    return c->D1 * e * e + c->dE;
+  }
+  const double d = x - c->qs;
+  return c->dV * std::exp(-d * d / (2.0 * c->sigma * c->sigma));
 }
 
 int qhfpe_destroy(qhfpe_t* h) {
@@ -554,6 +666,8 @@ int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
   const int c = cells_per_thread == 0 ? tile_default((int)h->L.elem, h->ns, h->p.np) : cells_per_thread;
   if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c))
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
+  if (h->qcoup && c != kTileWave)
+    return fail(QHFPE_EUNSUPPORTED, "a q-dependent coupling needs the wave variant (tile 1)");
   h->cpt = c;
   return QHFPE_OK;
 }
@@ -575,6 +689,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   int rc = QHFPE_OK;
   for (int c : candidates) {
     if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c)) continue;
+    if (h->qcoup && c != kTileWave) continue;
     h->cpt = c;
     StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
     hipError_t e = h->launch(a);  // warm-up

@@ -44,9 +44,10 @@ inline bool cpt_supported(int elem_bytes, int ns, int cpt) { return cpt_supporte
 inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
 
 // Tile code of the wave-independent stage variant (stage_wave.hpp): one
-// wave per pair of q columns, two states and np = 256 only.
+// wave per 512/np q columns, two states and np = 128 or 256.
 constexpr int kTileWave = 1;
 constexpr int kMaxGroups = 4;  // member groups (streams) of qhfpe_step
+constexpr int kWaveTables = 5;  // multiplier planes of the wave variant
 constexpr int kWaveTasksPerBlock = 4;  // waves per workgroup of the wave variant
 inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
 // q columns per task of the wave variant (a lane holds np / 64 p nodes)
@@ -67,10 +68,12 @@ struct StageArgs {
   const void* twiddle2;  // [n1][n2+1] complex exp(+2 pi i (n2 k1 mod np)/np), state precision
   const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
   const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
-  const void* mtab;      // wave variant: [3][nq][16][np/16] = dtab 0, dtab 1, gtab / 2, entry (k1, k2) at m = k1 + 16 k2
+  const void* mtab;      // wave variant: [kWaveTables][nq][n1][n2] = dtab 0, dtab 1, gtab / 2, U_01(q + r/2),
+                         // U_01(q - r/2) (both / (hbar np)), entry (k1, k2) at m = k1 + n1 k2
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
   int slot;
+  int qcoup;  // 1: q-dependent coupling through the r-space multiply (wave variant, two states)
   int nq;
   int depth;
   int ntiles;

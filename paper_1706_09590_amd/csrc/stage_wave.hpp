@@ -73,7 +73,9 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
   }
 }
 
-template <typename T, int NP>
+// QC: q-dependent diabatic coupling U_01(q), applied in the r-space multiply
+// (it mixes the packed-diagonal and coherence transforms of a column).
+template <typename T, int NP, bool QC>
 __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageArgs a) {
   using W = WavePlan<NP>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
@@ -322,7 +324,7 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   T mulA[I2][N2], mulB[I2][N2];
   {
     const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
-    const rsrc_t rt = make_rsrc(a.mtab, 3u * tbytes);
+    const rsrc_t rt = make_rsrc(a.mtab, (unsigned)kWaveTables * tbytes);
 #pragma unroll
     for (int t = 0; t < I2; ++t) {
       const int item = lane + 64 * t;
@@ -339,6 +341,29 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
         for (int j = 0; j < 4; ++j) {
           mulA[t][k2 + j] = qa.v[j];
           mulB[t][k2 + j] = qb.v[j];
+        }
+      }
+    }
+  }
+  // q-dependent coupling: U_01(q + r/2), U_01(q - r/2) of this lane's rows
+  T cP[QC ? I2 : 1][QC ? N2 : 1], cM[QC ? I2 : 1][QC ? N2 : 1];
+  if constexpr (QC) {
+    const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
+    const rsrc_t rt = make_rsrc(a.mtab, (unsigned)kWaveTables * tbytes);
+#pragma unroll
+    for (int t = 0; t < I2; ++t) {
+      const int item = lane + 64 * t;
+      const int f = item / N1, k1 = item % N1;
+      const int qc = min(q0 + f % C, nq - 1);
+      const unsigned row = ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; k2 += 4) {
+        const Quad<T> qp = buf_load4(rt, 3u * tbytes + row + k2 * ES, 0, T(0));
+        const Quad<T> qm = buf_load4(rt, 4u * tbytes + row + k2 * ES, 0, T(0));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cP[t][k2 + j] = qp.v[j];
+          cM[t][k2 + j] = qm.v[j];
         }
       }
     }
@@ -384,6 +409,14 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
     const int pbase = (k1 == 0) ? N2 : (N2 - 1) + (N2 + 1) * (N1 - k1);
     const T* pr = re + pbase;
     const T* pi = im + pbase;
+    // the other transform of the same column (q-dependent coupling only)
+    const int fi = item / N1, kind = fi / C;
+    const T* const ore = re_of(fi % C + C * (1 - kind));
+    const T* const ozr = ore + (N2 + 1) * k1;
+    const T* const ozi = ore + LDP + (N2 + 1) * k1;
+    const T* const opr = ore + pbase;
+    const T* const opi = ore + LDP + pbase;
+    const T hk = kind ? T(0.5) : T(1);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const cx<T> z = {zr[k2], zi[k2]};
@@ -394,6 +427,18 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
       const T sA = mulA[t][k2] + mulB[t][k2], dA = mulA[t][k2] - mulB[t][k2];
       const cx<T> u = {sA * z.re + dA * zp.re, sA * z.im + dA * zp.im};
       yk[t][k2] = {u.im + e * z.re, -u.re + e * z.im};
+      if constexpr (QC) {
+        // Z, Z' = the other transform of this column at m and conj at -m:
+        //   packed diagonals += (c+ + i c-) Z - (c- + i c+) Z'          (Z = coherence)
+        //   coherence        += (-c+ + i c-)/2 Z + (c+ + i c-)/2 Z'     (Z = packed diagonals)
+        const cx<T> zo = {ozr[k2], ozi[k2]};
+        const cx<T> zop = {opr[-k2], -opi[-k2]};
+        const T xp = hk * cP[t][k2], xm = hk * cM[t][k2];
+        const cx<T> al = {kind ? -xp : xp, xm};
+        const cx<T> be = {kind ? xp : -xm, kind ? xm : -xp};
+        yk[t][k2].re += al.re * zo.re - al.im * zo.im + be.re * zop.re - be.im * zop.im;
+        yk[t][k2].im += al.re * zo.im + al.im * zo.re + be.re * zop.im + be.im * zop.re;
+      }
     }
     SmallDft<N2, -1, T>::run(yk[t]);
   }
@@ -461,12 +506,18 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
 
 template <typename T>
 hipError_t launch_stage_wave(int np, const StageArgs& a, int nblocks, hipStream_t s) {
-  switch (np) {
-    case 128:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 128>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
-      return hipGetLastError();
+  switch (np * 2 + (a.qcoup ? 1 : 0)) {
     case 256:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 256>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
+      hipLaunchKernelGGL((stage_wave_kernel<T, 128, false>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
+      return hipGetLastError();
+    case 257:
+      hipLaunchKernelGGL((stage_wave_kernel<T, 128, true>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
+      return hipGetLastError();
+    case 512:
+      hipLaunchKernelGGL((stage_wave_kernel<T, 256, false>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
+      return hipGetLastError();
+    case 513:
+      hipLaunchKernelGGL((stage_wave_kernel<T, 256, true>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
       return hipGetLastError();
     default:
       return hipErrorInvalidValue;

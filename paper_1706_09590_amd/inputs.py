@@ -81,6 +81,33 @@ TWO_D_SPECTRUM = dict(
     n3_steps=4000, stride3=1)
 
 
+def paper_surfaces_params(w0: float = 100.0, w1: float = 80.0, D0: float = 70000.0, D1: float = 50000.0,
+                          dE: float = 1000.0, dV: float = 600.0, q0: float = 0.0, q1: float = 18.98,
+                          qs: float = 10.28, sigma: float = 2.0) -> dict:
+    """Sec. III model in the dimensionless q-bar, energies in units of
+    hbar omega_0 (inputs in cm^-1): displaced Morse diagonals with width
+    a_j = omega_j / sqrt(2 D_j omega_0) (the reading that reproduces the
+    printed resonance frequencies) and a Gaussian coupling.  Field names of
+    qhfpe_morse_gauss."""
+    return dict(D0=D0 / w0, D1=D1 / w0, a0=w0 / math.sqrt(2.0 * D0 * w0), a1=w1 / math.sqrt(2.0 * D1 * w0),
+                q0=q0, q1=q1, dE=dE / w0, dV=dV / w0, qs=qs, sigma=sigma)
+
+
+# The paper's own workload (Sec. III): Morse/Gaussian surfaces, mesh
+# N_p x N_q = 128 x 512 on -25 <= p <= 25, -20 <= q <= 80, underdamped bath
+# zeta = 40, gamma = 500 cm^-1 (0.4 and 5 omega_0), T = 300 K (beta hbar
+# omega_0 = 0.48), depth N = 5; m = hbar = omega_0 = 1.  RK4 with dt = 0.001
+# (the surfaces reach ~1400 omega_0 at the q edges, which bounds the step);
+# linear absorption R1 over t = 20 / omega_0 (~1 ps), sampled every step.
+PAPER_ABSORPTION = dict(
+    model=dict(n_states=2, nq=512, np=128, q_min=-20.0, q_max=80.0, p_min=-25.0, p_max=25.0,
+               depth=5, zeta=0.4, gamma=5.0, beta=0.48, dt=0.001,
+               poly=[[[0.0] * 5, [0.0] * 5], [[0.0] * 5, [0.0] * 5]], mu=[[0.0, 1.0], [1.0, 0.0]],
+               mass=1.0, hbar=1.0, low_temp_correction=True),
+    surfaces=paper_surfaces_params(), nsteps=20000, stride=1, thermal_omega=1.0,
+    omega_range=(150.0, 250.0), n_omega=2001)
+
+
 # Uneven batched sweep: 256 members on grids 96^2..256^2, depths 4..10, a
 # quarter of them three-state, random Drude baths; 5000 RK4 steps of 0.002
 # (sampled every step; members that need it take RK4 substeps).

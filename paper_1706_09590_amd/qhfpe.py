@@ -44,6 +44,14 @@ class Params(ctypes.Structure):
     ]
 
 
+POTENTIAL_FN = ctypes.CFUNCTYPE(_c_dbl, _c_i32, _c_i32, _c_dbl, _vp)
+
+
+class MorseGauss(ctypes.Structure):
+    """qhfpe_morse_gauss: displaced Morse diagonals and a Gaussian coupling."""
+    _fields_ = [(n, _c_dbl) for n in ("D0", "D1", "a0", "a1", "q0", "q1", "dE", "dV", "qs", "sigma")]
+
+
 class QHFPEError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"qhfpe error {code}: {msg}")
@@ -73,6 +81,8 @@ def lib():
         "qhfpe_set_tile": ([_vp, _c_i32], _c_int),
         "qhfpe_autotune": ([_vp, _c_i32, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_set_streams": ([_vp, _c_i32], _c_int),
+        "qhfpe_set_potential": ([_vp, _vp, _vp], _c_int),
+        "qhfpe_morse_gauss_potential": ([_c_i32, _c_i32, _c_dbl, _vp], _c_dbl),
         "qhfpe_get_streams": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
         "qhfpe_apply_dipole": ([_vp, _c_i32], _c_int),
@@ -202,6 +212,20 @@ class Propagator:
 
     def set_tile(self, cells_per_thread: int):
         _check(lib().qhfpe_set_tile(self.handle, int(cells_per_thread)))
+
+    def set_potential(self, fn):
+        """Surfaces from a Python function fn(j, l, x) -> U_jl(x) (j <= l),
+        evaluated by the library on the host while it rebuilds the r-space
+        multipliers (qhfpe_set_potential)."""
+        cb = POTENTIAL_FN(lambda j, l, x, ctx: float(fn(j, l, x)))
+        _check(lib().qhfpe_set_potential(self.handle, ctypes.cast(cb, _vp), None))
+
+    def set_potential_morse_gauss(self, **params):
+        """The Morse/Gaussian surfaces of Sec. III, evaluated by the library's
+        own qhfpe_morse_gauss_potential (params: MorseGauss fields)."""
+        c = MorseGauss(**{k: float(v) for k, v in params.items()})
+        fn = ctypes.cast(lib().qhfpe_morse_gauss_potential, _vp)
+        _check(lib().qhfpe_set_potential(self.handle, fn, ctypes.byref(c)))
 
     def set_streams(self, groups: int):
         """Member groups of step(): 1 = one launch per stage, 2..4 = that many
