@@ -110,6 +110,9 @@ def main():
                     help="also time the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
     ap.add_argument("--two-d-scale", type=int, default=1,
                     help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
+    ap.add_argument("--paper", action="store_true",
+                    help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
+    ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
                          "a quarter three-state, 5000 steps, FP32 state)")
@@ -236,6 +239,8 @@ def main():
         line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale)
     if args.sweep:
         line["uneven_sweep"] = uneven_sweep(args.sweep_steps)
+    if args.paper:
+        line["paper_workload"] = paper_workload(args.paper_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(inputs.model_dict(base, zeta=1.0))
         line["cpu_baseline"] = cb
@@ -265,6 +270,54 @@ def uneven_sweep(nsteps: int = 0):
                 substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
                 cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
                 finite=bool(all(np.all(np.isfinite(r)) for r in R)))
+
+
+def paper_workload(nsteps: int = 0):
+    """The paper's own model (Sec. III): Morse/Gaussian surfaces with a
+    q-dependent coupling, 128 x 512 mesh, depth 5, underdamped bath; linear
+    absorption R1 every step.  FP64 state, then FP32 state with its spectrum
+    error against FP64.  Reports wall time and cell-updates/s of each
+    propagation, dt times the power-iteration spectral radius (RK4 is stable
+    below about 2.8) and the absorption maximum in cm^-1."""
+    import numpy as np
+    import torch
+
+    from paper_1706_09590_amd import inputs, qhfpe, sweep
+    w = inputs.PAPER_ABSORPTION
+    m = w["model"]
+    surf = w["surfaces"]
+    nsteps = nsteps or w["nsteps"]
+    dev = torch.device("cuda:0")
+    rho = float(sweep.spectral_radius(m, [(m["zeta"], m["gamma"], m["beta"])], iters=60,
+                                      prepare=lambda P: P.set_potential_morse_gauss(**surf))[0])
+    om = torch.linspace(w["omega_range"][0], w["omega_range"][1], w["n_omega"], dtype=torch.float64, device=dev)
+    cells = (m["depth"] + 1) * m["nq"] * m["np"]
+    out = dict(mesh=f"{m['np']} x {m['nq']} (p x q)", depth=m["depth"], rk4_steps=nsteps, dt=m["dt"],
+               dt_times_spectral_radius=rho * m["dt"])
+    spec = {}
+    for prec in ("fp64", "fp32"):
+        P = qhfpe.Propagator(m, batch=1, precision=prec, device=dev)
+        P.set_potential_morse_gauss(**surf)
+        P.init_thermal(w["thermal_omega"])
+        P.apply_dipole()
+        resp = torch.empty((1, nsteps // w["stride"] + 1), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.step(nsteps, w["stride"], out=resp)
+        s = qhfpe.spectrum_abs((1j / m["hbar"]) * resp[0], m["dt"] * w["stride"], om)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        P.close()
+        spec[prec] = s.cpu().numpy()
+        out[prec] = dict(wall_s=wall, cell_updates_per_s=cells * nsteps / wall, tile_variant=1,
+                         finite=bool(np.all(np.isfinite(spec[prec]))))
+    omn = om.cpu().numpy()
+    # omega in units of omega_0 = 100 cm^-1
+    out["absorption_peak_cm-1"] = float(100.0 * omn[int(np.argmax(spec["fp64"]))])
+    out["vertical_gap_at_q0_cm-1"] = 100.0 * (surf["D1"] * (1 - np.exp(surf["a1"] * surf["q1"])) ** 2 + surf["dE"])
+    out["fp32_spectrum_max_rel_err_vs_fp64"] = float(np.max(np.abs(spec["fp32"] - spec["fp64"])) /
+                                                     np.max(np.abs(spec["fp64"])))
+    return out
 
 
 def two_d_spectrum(scale: int = 1):

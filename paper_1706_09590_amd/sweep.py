@@ -46,15 +46,19 @@ def _shape_key(model: dict):
             model["p_min"], model["p_max"])
 
 
-def spectral_radius(model: dict, baths, iters: int = 40, seed: int = 7, device=None, renorm_every: int = 8):
+def spectral_radius(model: dict, baths, iters: int = 40, seed: int = 7, device=None, renorm_every: int = 8,
+                    prepare=None):
     """Power-iteration estimate of the spectral radius of L for each bath
     (zeta, gamma, beta) on the grid of `model`: ||L^(k+1) W|| / ||L^k W||
     after `iters` applications, from a seeded random Hermitian hierarchy.
-    Returns a float64 array, one value per bath."""
+    prepare(P), if given, configures the probe handle first (e.g. its
+    surfaces).  Returns a float64 array, one value per bath."""
     import torch
     B = len(baths)
     P = qhfpe.Propagator(model, batch=B, precision="fp64", device=device)
     try:
+        if prepare is not None:
+            prepare(P)
         for i, (z, g, b) in enumerate(baths):
             P.set_member_bath(i, z, g, b)
         W = inputs.random_hierarchy(model["depth"], model["n_states"], model["nq"], model["np"], seed=seed,
