@@ -72,8 +72,10 @@ typedef struct qhfpe_params {
   double zeta, gamma, beta;    /* Drude bath: J(w) = (m zeta/pi) w gamma^2/(gamma^2 + w^2) */
   double dt;                   /* RK4 step */
   /* U_jl(x) = sum_k poly[j][l][k] x^k.  Diagonal entries: any quartic.
-   * Off-diagonal entries: constant couplings only (k >= 1 must be 0);
-   * poly must be symmetric in (j, l). */
+   * Off-diagonal entries: constants (applied pointwise); a q-dependent
+   * coupling (k >= 1 non-zero) needs two states and np = 128 or 256 (the
+   * wave variant's r-space multiply, see qhfpe_set_potential), else
+   * QHFPE_EUNSUPPORTED.  poly must be symmetric in (j, l). */
   double poly[QHFPE_MAX_STATES][QHFPE_MAX_STATES][5];
   double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES]; /* real symmetric Condon dipole */
 } qhfpe_params;

@@ -76,8 +76,9 @@ int validate(const qhfpe_params* p) {
       for (int k = 0; k < 5; ++k) {
         if (!std::isfinite(p->poly[j][l][k])) return fail(QHFPE_EINVAL, "poly has a non-finite entry");
         if (p->poly[j][l][k] != p->poly[l][j][k]) return fail(QHFPE_EINVAL, "poly must be symmetric");
-        if (j != l && k >= 1 && p->poly[j][l][k] != 0.0)
-          return fail(QHFPE_EUNSUPPORTED, "off-diagonal couplings must be constant (poly[%d][%d][%d] != 0)", j, l, k);
+        if (j != l && k >= 1 && p->poly[j][l][k] != 0.0 && !wave_supported(ns, p->np))
+          return fail(QHFPE_EUNSUPPORTED,
+                      "q-dependent couplings (poly[%d][%d][%d] != 0) need two states and np = 128 or 256", j, l, k);
       }
       if (!std::isfinite(p->mu[j][l]) || p->mu[j][l] != p->mu[l][j])
         return fail(QHFPE_EINVAL, "mu must be finite and symmetric");

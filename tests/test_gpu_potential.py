@@ -117,6 +117,30 @@ def test_q_dependent_coupling_propagation_parity():
         assert rel(st[b], W) < 1e-11, b
 
 
+@pytest.mark.parametrize("precision,np_", [("fp64", 256), ("fp64", 128), ("fp32", 256)])
+def test_q_dependent_polynomial_coupling_at_create(precision, np_):
+    """A polynomial coupling U_01 = 0.3 + 0.1 q + 0.02 q^2 in params.poly
+    takes the same r-space path; the oracle's polynomial surfaces are pinned
+    by the dense brute-force operator."""
+    say(f"polynomial q-dependent coupling {precision} np={np_}")
+    qc = [0.3, 0.1, 0.02, 0.0, 0.0]
+    poly = inputs.two_state_surfaces(0.3)
+    poly = [[poly[0][0], qc], [qc, poly[1][1]]]
+    d = small(np_=np_, nq=14, depth=2, poly=poly)
+    W = inputs.random_hierarchy(2, 2, 14, np_, seed=73 + np_)
+    P = qhfpe.Propagator(d, batch=1, precision=precision)
+    try:
+        with pytest.raises(qhfpe.QHFPEError):
+            P.set_tile(4)
+        P.set_state(torch.from_numpy(W[None]))
+        P.apply_rhs()
+        got = P.get_state().cpu().numpy()[0]
+    finally:
+        P.close()
+    err = rel(got, O.rhs(oracle_model(d), W))
+    assert err < (1e-12 if precision == "fp64" else 1e-5), err
+
+
 def test_polynomial_function_reproduces_params_poly():
     """The same quartic surfaces given as a function give the same tables,
     hence the same result bit for bit (constant coupling: pointwise path)."""

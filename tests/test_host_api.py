@@ -51,6 +51,39 @@ def test_parameter_validation(override, code):
     assert qhfpe.lib().qhfpe_last_error().decode() != ""
 
 
+def test_q_dependent_polynomial_coupling_accepted_where_the_wave_variant_exists():
+    qc = [[[0, 0, .5, 0, 0], [0.3, 0.1, 0.02, 0, 0]], [[0.3, 0.1, 0.02, 0, 0], [1, 0, .5, 0, 0]]]
+    for np_ in (128, 256):
+        m = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], np=np_, poly=qc)
+        assert qhfpe.workspace_bytes(m) > 0
+    with pytest.raises(qhfpe.QHFPEError) as ei:
+        qhfpe.workspace_bytes(inputs.model_dict(inputs.SMALL_ABSORPTION["model"], np=64, poly=qc))
+    assert ei.value.code == qhfpe.EUNSUPPORTED
+
+
+def test_morse_gauss_surfaces_on_the_host():
+    """qhfpe_morse_gauss_potential is host code: with the parameters of Sec.
+    III (cm^-1, Morse width omega_j / sqrt(2 D_j omega_0)) it gives the
+    printed resonance frequencies nu_0 = 20000 and nu_1 = 10083 cm^-1 to
+    0.1%, and agrees with the oracle's surfaces."""
+    import numpy as np
+
+    from oracle import qhfpe_oracle as O
+    w0, w1, D0, D1 = 100.0, 80.0, 70000.0, 50000.0
+    par = dict(D0=D0, D1=D1, a0=w0 / np.sqrt(2 * D0 * w0), a1=w1 / np.sqrt(2 * D1 * w0), q0=0.0, q1=18.98,
+               dE=1000.0, dV=600.0, qs=10.28, sigma=2.0)
+    c = qhfpe.MorseGauss(**par)
+    U = lambda j, l, x: qhfpe.lib().qhfpe_morse_gauss_potential(j, l, x, ctypes.byref(c))  # noqa: E731
+    assert abs((U(1, 1, 0.0) - U(0, 0, 0.0)) / 20000.0 - 1) < 1e-3
+    assert abs((U(0, 0, 18.98) - U(1, 1, 18.98)) / 10083.0 - 1) < 1e-3
+    ref = O.paper_surfaces(**par)
+    for x in (-20.0, -3.3, 0.0, 10.28, 18.98, 55.5, 80.0):
+        r = ref(x)
+        for j, l in ((0, 0), (1, 1), (0, 1), (1, 0)):
+            assert abs(U(j, l, x) - r[j, l]) <= 1e-12 * max(1.0, abs(r[j, l])), (j, l, x)
+    assert np.isnan(U(2, 0, 0.0)) and np.isnan(U(-1, 0, 0.0))
+
+
 def test_batch_and_precision_validation():
     m = inputs.SMALL_ABSORPTION["model"]
     p = qhfpe.make_params(m, 0, "fp64")
