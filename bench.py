@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
     ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
+    ap.add_argument("--sweep-streams", type=int, default=12, help="batches of the sweep run concurrently")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
                          "a quarter three-state, 5000 steps, FP32 state)")
@@ -238,7 +239,7 @@ def main():
     if args.two_d:
         line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale)
     if args.sweep:
-        line["uneven_sweep"] = uneven_sweep(args.sweep_steps)
+        line["uneven_sweep"] = uneven_sweep(args.sweep_steps, args.sweep_streams)
     if args.paper:
         line["paper_workload"] = paper_workload(args.paper_steps)
     if not args.no_cpu_baseline:
@@ -247,10 +248,11 @@ def main():
     print(json.dumps(line, default=float))
 
 
-def uneven_sweep(nsteps: int = 0):
+def uneven_sweep(nsteps: int = 0, streams: int = 12):
     """Wall time of the uneven batched sweep: plan (spectral radius and
     substeps per member, reported apart), then all members as batches of
-    like-shaped members on four concurrent streams, FP32 state, R1 every step."""
+    like-shaped members on concurrent streams (`streams` at a time), FP32 state,
+    R1 every step."""
     import numpy as np
     import torch
 
@@ -263,10 +265,11 @@ def uneven_sweep(nsteps: int = 0):
     subs, batches = sweep.plan(members, w["dt"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=4, batches=batches)
+    R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=streams, batches=batches)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return dict(wall_s=t2 - t1, plan_s=t1 - t0, members=len(members), batches=len(batches), rk4_steps=nsteps,
+                batch_streams=streams,
                 substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
                 cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
                 finite=bool(all(np.all(np.isfinite(r)) for r in R)))

@@ -22,7 +22,10 @@
 //    per lane in the two passes (every lane busy), r-space multiply in place
 //    (all lanes read their own and partner rows before any lane writes),
 //    inverse transform;
-//  - constant diabatic coupling: pointwise commutator in p.
+//  - constant diabatic coupling: pointwise commutator in p, added while the
+//    last component is computed; a q-dependent coupling U_01(q) instead
+//    enters the r-space multiply (QC instantiation), where it mixes the
+//    packed-diagonal and coherence transforms of a column.
 #pragma once
 
 #include "device_common.hpp"
