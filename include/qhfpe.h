@@ -176,7 +176,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen);
  * grouping: every member is computed by the same kernels in the same order.
  * groups: 1 = one launch per stage for all members; 2..4 = that many ranges
  * (capped at the batch size); 0 = default (one group per member for batches
- * of up to 3 members, 2 groups for 4..8 members, else 1).  Only qhfpe_step (and qhfpe_relax through it) uses the groups.
+ * of up to 3 members, 2 groups for 4..16 members, else 1).  Only qhfpe_step (and qhfpe_relax through it) uses the groups.
  * QHFPE_EINVAL if groups is outside [0, 4]. */
 int qhfpe_set_streams(qhfpe_t* h, int32_t groups);
 

@@ -314,11 +314,11 @@ struct qhfpe_handle {
 
   // Default for small batches, where one launch per stage leaves most SIMDs
   // with two or three waves that all load, then all transform, in step: one
-  // group per member up to three members, two groups for 4..8 members; one
-  // group above that.
+  // group per member up to three members, two groups for 4..16 members; one
+  // group above that (no gain measured from 32 members on).
   int groups() const {
     int want = groups_req;
-    if (want == 0) want = p.batch <= 3 ? p.batch : (p.batch <= 8 ? 2 : 1);
+    if (want == 0) want = p.batch <= 3 ? p.batch : (p.batch <= 16 ? 2 : 1);
     return std::min(want, p.batch);
   }
 

@@ -109,7 +109,7 @@ def test_grouped_step_against_oracle():
 
 def test_default_rule_and_limits():
     d = model(nq=12, np_=128, depth=1)
-    for batch, want in ((1, 1), (2, 2), (3, 3), (4, 2), (8, 2), (9, 1)):
+    for batch, want in ((1, 1), (2, 2), (3, 3), (4, 2), (16, 2), (17, 1)):
         P = qhfpe.Propagator(d, batch=batch, precision="fp64")
         assert P.streams() == want, batch
         P.set_streams(4)
