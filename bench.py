@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
     ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
-    ap.add_argument("--sweep-streams", type=int, default=12, help="batches of the sweep run concurrently")
+    ap.add_argument("--sweep-streams", type=int, default=1, help="batches of the sweep run concurrently")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
                          "a quarter three-state, 5000 steps, FP32 state)")
@@ -248,7 +248,7 @@ def main():
     print(json.dumps(line, default=float))
 
 
-def uneven_sweep(nsteps: int = 0, streams: int = 12):
+def uneven_sweep(nsteps: int = 0, streams: int = 1):
     """Wall time of the uneven batched sweep: plan (spectral radius and
     substeps per member, reported apart), then all members as batches of
     like-shaped members on concurrent streams (`streams` at a time), FP32 state,

@@ -41,7 +41,9 @@ constexpr bool cpt_supported_c(int elem_bytes, int ns, int cpt) {
                    : (elem_bytes == 8 ? cpt == 2 : (cpt == 2 || cpt == 4));
 }
 inline bool cpt_supported(int elem_bytes, int ns, int cpt) { return cpt_supported_c(elem_bytes, ns, cpt); }
-inline int cpt_default(int elem_bytes, int ns) { return (elem_bytes == 8 && ns == 3) ? 2 : 4; }
+// Three states: 2 cells per thread in both precisions (with 4, the LDS of a
+// 256-thread workgroup leaves room for one workgroup per CU at np = 256).
+inline int cpt_default(int /*elem_bytes*/, int ns) { return (ns == 3) ? 2 : 4; }
 
 // Tile code of the wave-independent stage variant (stage_wave.hpp): one
 // wave per 512/np q columns, two states and np = 128 or 256.

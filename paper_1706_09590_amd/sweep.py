@@ -4,9 +4,11 @@ depths, state counts and baths, run as batches of like-shaped members.
 The linear-absorption protocol of Sec. III (thermal state, impulsive mu^x,
 R1(t) = (i/hbar) Tr{mu W^(0)(t)}, Eq. (R1)) is run for every member.
 Members that share a grid, a depth, a state count and a number of RK4
-substeps form one batch (one library handle, one launch per stage); the
-batches run concurrently, each on its own stream from its own host thread
-(the library calls release the interpreter lock).
+substeps form one batch (one library handle, one launch per stage and
+member group, with the stage variant picked by qhfpe_autotune).  The batches
+run one after another by default: a tuned batch fills the GPU, and running
+several at once (each on its own stream from its own host thread; the
+library calls release the interpreter lock) was slower.
 
 RK4 is only stable for dt |lambda| below about 2.8; members with strong,
 hot baths need substeps.  Each member's spectral radius is estimated by
@@ -101,7 +103,7 @@ def plan(members, dt: float, estimate_iters: int = 40, device=None):
     return subs, batches
 
 
-def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams: int = 4, batches=None,
+def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams: int = 1, batches=None,
               thermal_omega: float = 1.0, device=None):
     """R1(t) for every member, sampled every dt for nsteps steps.
 
@@ -126,6 +128,7 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 for j, i in enumerate(ids):
                     m = members[i]
                     P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
+                P.autotune(5)  # the fastest stage variant for this batch's shape and size
                 P.init_thermal(thermal_omega)
                 P.apply_dipole()
                 tr = P.step(nsteps * subs, subs)
