@@ -299,14 +299,17 @@ def paper_workload(nsteps: int = 0):
                dt_times_spectral_radius=rho * m["dt"])
     # W_eq: FP64 real-time relaxation of the full hierarchy from the harmonic
     # thermal state (reported apart)
-    E = qhfpe.Propagator(m, batch=1, precision="fp64", device=dev)
+    # at the largest stable RK4 step (the stationary state does not depend on it)
+    dt_relax = 2.0 / rho
+    E = qhfpe.Propagator(inputs.model_dict(m, dt=dt_relax), batch=1, precision="fp64", device=dev)
     E.set_potential_morse_gauss(**surf)
     E.init_thermal(w["thermal_omega"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps, res = E.relax(w["relax_tol"], w["relax_max_steps"], 1000)
     torch.cuda.synchronize()
-    out.update(equilibration_s=time.perf_counter() - t0, equilibration_steps=steps, equilibration_residual=res)
+    out.update(equilibration_s=time.perf_counter() - t0, equilibration_steps=steps, equilibration_residual=res,
+               equilibration_dt=dt_relax)
     W_eq = E.get_state()
     E.close()
     spec = {}
@@ -349,7 +352,10 @@ def two_d_spectrum(scale: int = 1):
     t2s = w["t2_steps"][:: scale]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    W_eq, steps, res = response.equilibrate(m, tol=1e-10, max_steps=100000, check_every=500)
+    # relaxation at the largest stable RK4 step (the stationary state does not
+    # depend on the step)
+    dt_relax = response.relax_step(m)
+    W_eq, steps, res = response.equilibrate(m, tol=1e-10, max_steps=100000, check_every=500, dt=dt_relax)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     R3 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp32")

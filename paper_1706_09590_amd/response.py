@@ -22,16 +22,34 @@ from . import qhfpe
 
 
 def equilibrate(model: dict, tol: float = 1e-10, max_steps: int = 200000, check_every: int = 200,
-                omega: float = 1.0, device=None):
+                omega: float = 1.0, device=None, dt=None):
     """FP64 real-time relaxation of the full hierarchy from the harmonic
     thermal Wigner function (frequency omega) until ||L W|| / ||W|| < tol.
+    dt: the relaxation step (default: the model's).  An RK4 step leaves W
+    unchanged exactly when L W = 0, so the stationary state does not depend
+    on dt; the largest stable step (see relax_step) reaches it in the fewest
+    steps.
     Returns (W_eq canonical complex128 [1][N+1][ns][ns][nq][np], steps, residual)."""
+    if dt is not None:
+        model = dict(model, dt=float(dt))
     P = qhfpe.Propagator(model, batch=1, precision="fp64", device=device)
     P.init_thermal(omega)
     steps, res = P.relax(tol, max_steps, check_every)
     W = P.get_state()
     P.close()
     return W, steps, res
+
+
+def relax_step(model: dict, margin: float = 2.0, device=None, prepare=None) -> float:
+    """A large stable RK4 step margin / rho for relaxation, with rho the
+    power-iteration spectral radius of L (RK4 is stable for |dt lambda|
+    below about 2.8; the margin leaves room for power iteration's
+    underestimate over the many steps of a relaxation).  prepare(P)
+    configures the probe handle (surfaces)."""
+    from . import sweep
+    rho = sweep.spectral_radius(model, [(model["zeta"], model["gamma"], model["beta"])], device=device,
+                                prepare=prepare)[0]
+    return float(margin / rho)
 
 
 def linear_response(model: dict, nsteps: int, stride: int = 1, precision: str = "fp64", W0=None,

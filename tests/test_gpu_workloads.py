@@ -122,16 +122,20 @@ def test_production_full_length_properties():
         assert spec_err(spec["fp32"][i], spec["fp64"][i]) < 1e-4
 
 
-def test_equilibrium_is_the_brownian_oscillator_state():
+@pytest.mark.parametrize("step", ["model", "largest_stable"])
+def test_equilibrium_is_the_brownian_oscillator_state(step):
     """a2: FP64 relaxation of the full hierarchy on the GPU.  With uncoupled
     states and a harmonic ground surface, level 0 relaxes to the state whose
     moments the generalized Langevin equation fixes, and the result is
-    stationary under the oracle's operator."""
+    stationary under the oracle's operator.  The stationary state does not
+    depend on the relaxation step: the model's dt and the largest stable
+    step (2 / spectral radius) reach the same state."""
     d = dict(inputs.SMALL_ABSORPTION["model"])
     d.update(nq=64, np=64, q_min=-8.0, q_max=8.0, p_min=-8.0, p_max=8.0, depth=8, dt=0.01,
              poly=[[[0, 0, 0.5, 0, 0], [0] * 5], [[0] * 5, [5.0, 0, 0.5, 0, 0]]])
-    W, steps, res = response.equilibrate(d, tol=1e-9, max_steps=40000, check_every=500)
-    say(f"relaxed in {steps} steps, residual {res:.2e}")
+    dt = None if step == "model" else response.relax_step(d)
+    W, steps, res = response.equilibrate(d, tol=1e-9, max_steps=40000, check_every=500, dt=dt)
+    say(f"relaxed in {steps} steps (dt {dt or d['dt']:.4g}), residual {res:.2e}")
     assert res < 1e-9
     Wn = W.cpu().numpy()[0]
     m = oracle_model(d)
