@@ -17,12 +17,18 @@
  *    the last failure on the calling thread is qhfpe_last_error().
  *  - Every pointer named d_* is device memory on the GPU that is current
  *    when the handle is created; h_* is host memory.  The caller owns all
- *    memory, including the workspace; the library allocates nothing on the
- *    device and keeps non-owning pointers only.
- *  - Work is enqueued on the handle's stream.  qhfpe_set_state,
- *    qhfpe_step, qhfpe_residual and qhfpe_relax synchronise that stream
- *    before they return (they read a result or a status flag back); the
- *    other calls are asynchronous.
+ *    memory, including the workspace; the library allocates no device
+ *    memory and keeps non-owning pointers only (it does create the streams
+ *    and events of qhfpe_step's member groups, see qhfpe_set_streams).
+ *  - Work is enqueued on the handle's stream (qhfpe_step's member groups
+ *    run on their own streams between an event fork and join on it).
+ *    qhfpe_create, qhfpe_set_state, qhfpe_set_member_bath,
+ *    qhfpe_set_potential, qhfpe_autotune, qhfpe_step, qhfpe_residual and
+ *    qhfpe_relax synchronise that stream before they return (they upload
+ *    tables or read a result or a status flag back); the other calls are
+ *    asynchronous.
+ *  - A handle is used by one host thread at a time; different handles may
+ *    be used from different threads.
  *  - Canonical state layout ("canon"): interleaved complex128 (re, im)
  *    doubles, index [member][n][j][k][i][a] with n = 0..N, states j, k,
  *    q nodes i (slowest of the grid) and p nodes a (fastest).

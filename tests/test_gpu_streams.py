@@ -69,6 +69,29 @@ def test_groupings_agree_bitwise(precision, tile):
             assert np.array_equal(a, b), (g, np.max(np.abs(a - b)))
 
 
+def test_groupings_agree_without_recording_and_for_zero_steps():
+    """record=False takes the trace after the join; nsteps = 0 returns the
+    t = 0 sample only."""
+    say("groupings: no recording, zero steps")
+    d = model(nq=14, np_=128, depth=2)
+    out = {}
+    for g in (1, 2):
+        P = qhfpe.Propagator(d, batch=2, precision="fp64")
+        try:
+            P.set_member_bath(1, *BATHS[1])
+            P.set_streams(g)
+            P.init_thermal(1.0)
+            P.apply_dipole()
+            P.step(7, 1, record=False)
+            r0 = P.step(0, 1).cpu().numpy()
+            assert r0.shape == (2, 1)
+            out[g] = (r0, P.response().cpu().numpy(), P.get_state().cpu().numpy())
+        finally:
+            P.close()
+    for a, b in zip(out[2], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_grouping_on_a_user_stream():
     """The fork and join order the groups after earlier work and before later
     work on the handle's own (non-default) stream."""
