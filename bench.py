@@ -68,12 +68,15 @@ def cpu_baseline(model: dict, nsteps: int = 30):
                 poly=np.array(model["poly"]), mu=np.array(model["mu"]))
     W = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
     tables = O.moyal_tables(m)
-    W = O.rk4_step(m, W, tables=tables)  # warm caches
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        W = O.rk4_step(m, W, tables=tables)
-        O.trace_mu(m, W)
-    dt = time.perf_counter() - t0
+    # numpy may already be loaded with threaded BLAS pools: limit them here
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        W = O.rk4_step(m, W, tables=tables)  # warm caches
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            W = O.rk4_step(m, W, tables=tables)
+            O.trace_mu(m, W)
+        dt = time.perf_counter() - t0
     cells = (m.depth + 1) * m.nq * m.np_
     return dict(value=nsteps * cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=f"{nsteps} RK4 steps (+trace) of the 256x256 depth-8 two-state hierarchy, "
