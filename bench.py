@@ -125,7 +125,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the propagations of this workload "
-              "shard over independent batch members, and this build measures the single-GPU path.",
+              "shard over independent batch members; bench.py measures the one-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:

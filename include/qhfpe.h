@@ -227,7 +227,11 @@ int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every,
 
 /* Copy count members src[src_member..] -> dst[dst_member..] device to
  * device (multi-time protocol of Sec. III).  Both handles must share
- * n_states, nq, np, depth and precision; dst takes src's phase. */
+ * n_states, nq, np, depth and precision; dst takes src's phase.  Within
+ * one handle the two ranges must not overlap (QHFPE_EINVAL).  The copy is
+ * enqueued on dst's stream; when the handles' streams differ the call
+ * waits for src's stream before the copy and for the copy before it
+ * returns, so neither handle's later work can race with it. */
 int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst,
                        int32_t dst_member, int32_t count);
 

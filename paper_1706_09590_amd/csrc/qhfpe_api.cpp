@@ -500,8 +500,9 @@ int norms(qhfpe_t* h, const void* buf, std::vector<double>& out) {
 }
 
 // Multiplier tables from the surfaces U, uploaded to the handle (computed in
-// FP64 and rounded once to the state precision).  On return with an error
-// the handle's tables and coupling mode are unchanged.
+// FP64 and rounded once to the state precision).  When the surfaces are
+// rejected the handle's tables and coupling mode are unchanged; after a
+// failed upload (QHFPE_EHIP) the tables may be partly replaced.
 int install_surfaces(qhfpe_t* h, const Surfaces& U) {
   std::vector<double> dt, gt, ct, mt;
   bool coup_const = true;
@@ -949,12 +950,18 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int
   if (count < 0 || src_member < 0 || dst_member < 0 || src_member + count > src->p.batch ||
       dst_member + count > dst->p.batch)
     return fail(QHFPE_EINVAL, "member range out of bounds");
-  if (count == 0) return QHFPE_OK;
+  if (src == dst && src_member < dst_member + count && dst_member < src_member + count && src_member != dst_member)
+    return fail(QHFPE_EINVAL, "overlapping member ranges within one handle");
+  if (count == 0 || (src == dst && src_member == dst_member)) return QHFPE_OK;
   const size_t mb = (size_t)src->L.member_elems * src->L.elem;
-  if (src->stream != dst->stream) HIP_TRY(hipStreamSynchronize(src->stream));
+  // on different streams: src's pending steps finish before the copy reads
+  // its state, and the copy finishes before src's later work can change it
+  const bool two = src->stream != dst->stream;
+  if (two) HIP_TRY(hipStreamSynchronize(src->stream));
   HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst->y()) + dst_member * mb,
                          static_cast<const char*>(src->y()) + src_member * mb, count * mb,
                          hipMemcpyDeviceToDevice, dst->stream));
+  if (two) HIP_TRY(hipStreamSynchronize(dst->stream));
   dst->phase = src->phase;
   return QHFPE_OK;
 }

@@ -176,6 +176,19 @@ class Propagator:
         self.shape = (self.model["depth"] + 1, self.model["n_states"], self.model["n_states"],
                       self.model["nq"], self.model["np"])
 
+    # The library works on the handle's stream, torch on the caller's current
+    # stream: tensors handed to the library are ordered before its work, and
+    # tensors it fills are ordered before later torch work.
+    def _after_torch(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _before_torch(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().qhfpe_destroy(self.handle)
@@ -192,13 +205,16 @@ class Propagator:
         t = self.torch
         W = t.as_tensor(W, dtype=t.complex128, device=self.device).contiguous()
         self._keep = W
+        self._after_torch()
         _check(lib().qhfpe_set_state(self.handle, _ptr(W), int(phase), int(member)))
 
     def get_state(self, member: int = -1):
         t = self.torch
         n = self.batch if member < 0 else 1
         out = t.empty((n,) + self.shape, dtype=t.complex128, device=self.device)
+        self._after_torch()
         _check(lib().qhfpe_get_state(self.handle, _ptr(out), int(member)))
+        self._before_torch()
         return out
 
     @property
@@ -247,8 +263,11 @@ class Propagator:
         ptr = None
         if noise is not None:
             noise = t.as_tensor(noise, dtype=t.float64, device=self.device).contiguous()
+            if noise.numel() != self.model["nq"] * self.model["np"]:
+                raise ValueError(f"noise must have nq * np = {self.model['nq'] * self.model['np']} entries")
             self._noise = noise
             ptr = _ptr(noise)
+            self._after_torch()
         _check(lib().qhfpe_init_thermal(self.handle, float(omega), ptr))
 
     # -- dynamics ------------------------------------------------------------
@@ -263,13 +282,20 @@ class Propagator:
         n = nsteps // stride + 1
         if out is None:
             out = t.empty((self.batch, n), dtype=t.complex128, device=self.device)
+        elif (out.dtype != t.complex128 or tuple(out.shape) != (self.batch, n) or not out.is_contiguous()
+              or out.device != self.workspace.device):
+            raise ValueError(f"out must be a contiguous complex128 tensor of shape ({self.batch}, {n}) "
+                             f"on {self.workspace.device}")
+        self._after_torch()
         _check(lib().qhfpe_step(self.handle, int(nsteps), int(stride), _ptr(out)))
         return out
 
     def response(self):
         t = self.torch
         out = t.empty((self.batch,), dtype=t.complex128, device=self.device)
+        self._after_torch()
         _check(lib().qhfpe_response(self.handle, _ptr(out)))
+        self._before_torch()
         return out
 
     def apply_rhs(self):

@@ -257,3 +257,47 @@ def test_tile_variants_agree(precision):
     assert P.autotune(3) in (2, 4)
     with pytest.raises(qhfpe.QHFPEError):
         P.set_tile(3)
+
+
+def test_copy_members_within_a_handle_and_across_streams():
+    """A copy inside one handle duplicates a member exactly; overlapping
+    ranges inside one handle are rejected; a copy between handles on two
+    different streams sees src's finished steps and is not disturbed by
+    src's later steps."""
+    say("copy_members: same handle, overlap, two streams")
+    d = small_model(nq=16, np_=32, depth=2)
+    P = qhfpe.Propagator(d, batch=3)
+    P.set_member_bath(1, 1.0, 0.8, 0.7)
+    P.init_thermal(1.0)
+    P.apply_dipole()
+    P.step(5, 1, record=False)
+    P.copy_members_from(P, 1, 2, 1)
+    st = P.get_state().cpu().numpy()
+    np.testing.assert_array_equal(st[2], st[1])
+    for a, b, n in ((0, 1, 2), (1, 0, 2)):
+        with pytest.raises(qhfpe.QHFPEError) as e:
+            P.copy_members_from(P, a, b, n)
+        assert e.value.code == qhfpe.EINVAL
+    P.copy_members_from(P, 1, 1, 1)  # a copy onto itself changes nothing
+    np.testing.assert_array_equal(P.get_state().cpu().numpy(), st)
+    P.close()
+
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    A = qhfpe.Propagator(d, batch=1, stream=s1)
+    B = qhfpe.Propagator(d, batch=2, stream=s2)
+    with torch.cuda.stream(s1):
+        A.init_thermal(1.0)
+        A.apply_dipole()
+        A.step(40, 1, record=False)  # still running on s1 when the copy is issued
+    B.copy_members_from(A, 0, 1, 1)
+    with torch.cuda.stream(s1):
+        A.step(40, 1, record=False)  # must not change what B received
+    with torch.cuda.stream(s2):
+        got = B.get_state().cpu().numpy()[1]
+    R = qhfpe.Propagator(d, batch=1)
+    R.init_thermal(1.0)
+    R.apply_dipole()
+    R.step(40, 1, record=False)
+    np.testing.assert_array_equal(got, R.get_state().cpu().numpy()[0])
+    for h in (A, B, R):
+        h.close()
