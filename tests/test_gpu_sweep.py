@@ -77,3 +77,29 @@ def test_grouped_sweep_matches_the_oracle_per_member():
     R32, _ = sweep.run_sweep(members, nsteps, dt, precision="fp32", streams=2, batches=batches)
     for i in range(len(members)):
         assert np.linalg.norm(R32[i] - R[i]) / np.linalg.norm(R[i]) < 1e-4
+
+
+def test_full_sweep_sampled_members():
+    """All 256 members of the uneven sweep, in the launch configuration of
+    the sweep workload (planned batches and substeps, per-batch autotune,
+    FP32 state, batches one after another), for a few steps; members of the
+    smallest, a three-state and the largest shape against the FP64 oracle."""
+    w = inputs.UNEVEN_SWEEP
+    members = inputs.uneven_sweep_members(w["n_members"], w["seed"])
+    dt, nsteps = w["dt"], 6
+    subs, batches = sweep.plan(members, dt)
+    say(f"full sweep: {len(members)} members in {len(batches)} batches")
+    R, info = sweep.run_sweep(members, nsteps, dt, precision="fp32", batches=batches)
+    assert info["batches"] == len(batches)
+    assert all(r.shape == (nsteps + 1,) and np.all(np.isfinite(r)) for r in R)
+    shapes = [(96, 4, 2), (192, 8, 3), (256, 10, 2)]
+    picks = [next(i for i, m in enumerate(members) if (m["grid"], m["depth"], m["n_states"]) == s) for s in shapes]
+    for i in picks:
+        say(f"oracle member {i}: grid {members[i]['grid']}, depth {members[i]['depth']}, "
+            f"{members[i]['n_states']} states, {subs[i]} substeps")
+        m = oracle_model(inputs.model_dict(sweep.member_model(members[i], dt), dt=dt / subs[i]))
+        W0 = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
+        _, tr = O.propagate(m, W0, nsteps * int(subs[i]), int(subs[i]))
+        ref = (1j / m.hbar) * tr
+        err = np.linalg.norm(R[i] - ref) / np.linalg.norm(ref)
+        assert err < 1e-4, (i, err)

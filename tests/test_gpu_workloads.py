@@ -175,3 +175,42 @@ def test_third_order_response_and_2d_spectra(precision):
         tol = 1e-10 if precision == "fp64" else 1e-4
         assert spec_err(Ic[j].cpu().numpy(), Iref) < tol
         assert spec_err(It[j].cpu().numpy(), Tref) < tol
+
+
+def test_two_d_full_batch_sampled_members():
+    """The t3 batch of the 2D spectrum at its full size (1024 members of the
+    128x128 depth-6 hierarchy, FP32 state, the default stage variant and
+    member grouping, as the spectrum runs it).  Three members get seeded
+    random states and baths of their own; all others hold the thermal state
+    after mu^x.  After 10 steps the sampled members (and one thermal member)
+    match the FP64 oracle to the FP32 bars, and every thermal member gives
+    the same traces bit for bit."""
+    w = inputs.TWO_D_SPECTRUM
+    d = w["model"]
+    B = len(w["t1_steps"]) * len(w["t2_steps"])
+    picks = {0: (31, (0.2, 0.8, 0.7)), 511: (32, (1.5, 1.2, 2.0)), B - 1: (33, (0.05, 1.0, 3.0))}
+    shape = (d["depth"], d["n_states"], d["nq"], d["np"])
+    say(f"2D batch at full size: {B} members")
+    P = qhfpe.Propagator(d, batch=B, precision="fp32")
+    try:
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        for i, (seed, bath) in picks.items():
+            W0 = inputs.random_hierarchy(*shape, seed=seed, phase=1)
+            P.set_state(torch.from_numpy(W0[None]), phase=1, member=i)
+            P.set_member_bath(i, *bath)
+        tr = P.step(10, 5).cpu().numpy()
+        states = {i: P.get_state(member=i).cpu().numpy()[0] for i in list(picks) + [1]}
+    finally:
+        P.close()
+    thermal = [k for k in range(B) if k not in picks]
+    assert all(np.array_equal(tr[k], tr[thermal[0]]) for k in thermal)
+    cases = [(i, inputs.random_hierarchy(*shape, seed=seed, phase=1), bath) for i, (seed, bath) in picks.items()]
+    m1 = oracle_model(d)
+    cases.append((1, O.dipole_commutator(m1, O.thermal_initial_state(m1, 1.0)), (d["zeta"], d["gamma"], d["beta"])))
+    for i, W0, (z, g, b) in cases:
+        say(f"oracle member {i}")
+        m = oracle_model(inputs.model_dict(d, zeta=z, gamma=g, beta=b))
+        W, ref = O.propagate(m, W0, 10, 5)
+        assert rel(states[i], W) < 1e-5, i
+        assert rel(tr[i], ref) < 1e-4, i
