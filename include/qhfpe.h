@@ -68,7 +68,7 @@ typedef struct qhfpe_params {
   int32_t nq;                  /* q nodes, >= 4 */
   int32_t np;                  /* p nodes: 8,12,16,24,32,48,64,96,128,192 or 256 */
   int32_t depth;               /* hierarchy depth N >= 0 (levels 0..N) */
-  int32_t batch;               /* B >= 1 independent members sharing this model */
+  int32_t batch;               /* 1 <= B <= 65535 independent members sharing this model */
   int32_t precision;           /* QHFPE_FP64, or QHFPE_FP32_FP64RED (FP32 state, FP64 traces) */
   int32_t low_temp_correction; /* 1: c0 = (m zeta hbar gamma/2) cot(beta hbar gamma/2), c_delta = m zeta/beta - c0;
                                   0: c0 = m zeta/beta, c_delta = 0 */
@@ -243,7 +243,8 @@ int qhfpe_spectrum_abs(const double* d_series, int64_t n, double dt, const doubl
 
 /* Sec. III, Eqs. (I3), (nonreph), (reph) for one waiting time:
  * d_out[w3][w1] = Im sum_{t1,t3} c c dt1 dt3 e^{i w3 t3} (e^{i w1 t1} + e^{-i w1 t1}) R3[t1][t3].
- * d_r3: complex [n1][n3][2]; d_work: >= n1 * n_w3 * 2 doubles of scratch. */
+ * d_r3: complex [n1][n3][2]; d_work: >= n1 * n_w3 * 2 doubles of scratch;
+ * n1 and n_w3 at most 65535 (QHFPE_EINVAL otherwise). */
 int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3,
                         const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3,
                         double* d_work, double* d_out, void* stream);

@@ -59,7 +59,8 @@ int validate(const qhfpe_params* p) {
   if (!find_plan(p->np))
     return fail(QHFPE_EUNSUPPORTED, "np=%d not supported (8,12,16,24,32,48,64,96,128,192,256)", p->np);
   if (p->depth < 0 || p->depth > 64) return fail(QHFPE_EINVAL, "depth must be in [0, 64] (got %d)", p->depth);
-  if (p->batch < 1) return fail(QHFPE_EINVAL, "batch must be >= 1 (got %d)", p->batch);
+  // members index the second grid dimension of the pointwise kernels
+  if (p->batch < 1 || p->batch > 65535) return fail(QHFPE_EINVAL, "batch must be in [1, 65535] (got %d)", p->batch);
   if (p->precision != QHFPE_FP64 && p->precision != QHFPE_FP32_FP64RED)
     return fail(QHFPE_EINVAL, "unknown precision %d", p->precision);
   if (p->reserved != 0) return fail(QHFPE_EINVAL, "reserved must be 0");
@@ -84,6 +85,8 @@ int validate(const qhfpe_params* p) {
         return fail(QHFPE_EINVAL, "mu must be finite and symmetric");
     }
   const long double elems = (long double)p->batch * (p->depth + 1) * ns * ns * p->nq * p->np;
+  // (the cap also keeps a stage grid's count of q tiles x levels x members,
+  // about elems / (512 ns^2) plus levels x members, far below 2^31)
   if (elems > 4.0e11L) return fail(QHFPE_EINVAL, "state too large");
   // one hierarchy level of one member is addressed with 32-bit byte offsets
   const long double level_bytes = (long double)ns * ns * p->nq * p->np * 8.0L;
@@ -979,6 +982,7 @@ int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, 
                         void* stream) {
   if (!d_r3 || !d_w1 || !d_w3 || !d_work || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
   if (n1 < 1 || n3 < 1 || n_w1 < 1 || n_w3 < 1 || !(dt1 > 0) || !(dt3 > 0)) return fail(QHFPE_EINVAL, "bad sizes");
+  if (n1 > 65535 || n_w3 > 65535) return fail(QHFPE_EINVAL, "n1 and n_w3 must be <= 65535");
   HIP_TRY(launch_spectrum_corr(d_r3, n1, n3, dt1, dt3, d_w1, n_w1, d_w3, n_w3, d_work, d_out,
                                static_cast<hipStream_t>(stream)));
   return QHFPE_OK;

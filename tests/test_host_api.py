@@ -95,6 +95,16 @@ def test_batch_and_precision_validation():
     p = qhfpe.make_params(m, 1, "fp64")
     p.reserved = 1
     assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.EINVAL
+    # members index the pointwise kernels' second grid dimension
+    p = qhfpe.make_params(m, 65535, "fp32")
+    assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.OK
+    p = qhfpe.make_params(m, 65536, "fp32")
+    assert qhfpe.lib().qhfpe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == qhfpe.EINVAL
+    # spectral transform limits, checked before any device access
+    L = qhfpe.lib()
+    d = ctypes.c_void_p(256)  # never dereferenced: the sizes are rejected first
+    assert L.qhfpe_spectrum_corr(d, 65536, 4, 0.1, 0.1, d, 4, d, 4, d, d, None) == qhfpe.EINVAL
+    assert L.qhfpe_spectrum_corr(d, 4, 4, 0.1, 0.1, d, 4, d, 65536, d, d, None) == qhfpe.EINVAL
 
 
 def test_null_arguments_rejected_without_gpu():
