@@ -237,14 +237,15 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst,
 
 /* Sec. III, Eq. (I1) (and Eq. (transient-absorption) for an R3(t, T, 0)
  * series): d_out[w] = omega_w Im sum_s c_s dt exp(i omega_w s dt) R[s],
- * trapezoid weights c_s, no window.  d_series: complex [n][2]. */
+ * trapezoid weights c_s, no window.  d_series: complex [n][2], n >= 2
+ * (QHFPE_EINVAL otherwise: one sample spans no interval). */
 int qhfpe_spectrum_abs(const double* d_series, int64_t n, double dt, const double* d_omega,
                        int32_t n_omega, double* d_out, void* stream);
 
 /* Sec. III, Eqs. (I3), (nonreph), (reph) for one waiting time:
  * d_out[w3][w1] = Im sum_{t1,t3} c c dt1 dt3 e^{i w3 t3} (e^{i w1 t1} + e^{-i w1 t1}) R3[t1][t3].
  * d_r3: complex [n1][n3][2]; d_work: >= n1 * n_w3 * 2 doubles of scratch;
- * n1 and n_w3 at most 65535 (QHFPE_EINVAL otherwise). */
+ * n1, n3 >= 2 and n1, n_w3 <= 65535 (QHFPE_EINVAL otherwise). */
 int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3,
                         const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3,
                         double* d_work, double* d_out, void* stream);

@@ -424,9 +424,11 @@ def relax_to_equilibrium(m: Model, W: np.ndarray, tol: float = 1e-10,
 # ---------------------------------------------------------------------------
 
 def _trapezoid_weights(n: int) -> np.ndarray:
+    # the trapezoid rule over n >= 2 samples; one sample spans no interval
+    if n < 2:
+        raise ValueError("the trapezoid rule needs at least two samples")
     w = np.ones(n)
-    if n > 1:
-        w[0] = w[-1] = 0.5
+    w[0] = w[-1] = 0.5
     return w
 
 

@@ -972,7 +972,8 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int
 int qhfpe_spectrum_abs(const double* d_series, int64_t n, double dt, const double* d_omega, int32_t n_omega,
                        double* d_out, void* stream) {
   if (!d_series || !d_omega || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
-  if (n < 1 || n_omega < 1 || !(dt > 0)) return fail(QHFPE_EINVAL, "bad sizes");
+  // the trapezoid rule needs an interval: at least two samples
+  if (n < 2 || n_omega < 1 || !(dt > 0)) return fail(QHFPE_EINVAL, "need n >= 2 samples, n_omega >= 1, dt > 0");
   HIP_TRY(launch_spectrum_abs(d_series, n, dt, d_omega, n_omega, d_out, static_cast<hipStream_t>(stream)));
   return QHFPE_OK;
 }
@@ -981,7 +982,8 @@ int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, 
                         int32_t n_w1, const double* d_w3, int32_t n_w3, double* d_work, double* d_out,
                         void* stream) {
   if (!d_r3 || !d_w1 || !d_w3 || !d_work || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
-  if (n1 < 1 || n3 < 1 || n_w1 < 1 || n_w3 < 1 || !(dt1 > 0) || !(dt3 > 0)) return fail(QHFPE_EINVAL, "bad sizes");
+  if (n1 < 2 || n3 < 2 || n_w1 < 1 || n_w3 < 1 || !(dt1 > 0) || !(dt3 > 0))
+    return fail(QHFPE_EINVAL, "need n1, n3 >= 2 samples, n_w1, n_w3 >= 1, dt1, dt3 > 0");
   if (n1 > 65535 || n_w3 > 65535) return fail(QHFPE_EINVAL, "n1 and n_w3 must be <= 65535");
   HIP_TRY(launch_spectrum_corr(d_r3, n1, n3, dt1, dt3, d_w1, n_w1, d_w3, n_w3, d_work, d_out,
                                static_cast<hipStream_t>(stream)));

@@ -105,6 +105,10 @@ def test_batch_and_precision_validation():
     d = ctypes.c_void_p(256)  # never dereferenced: the sizes are rejected first
     assert L.qhfpe_spectrum_corr(d, 65536, 4, 0.1, 0.1, d, 4, d, 4, d, d, None) == qhfpe.EINVAL
     assert L.qhfpe_spectrum_corr(d, 4, 4, 0.1, 0.1, d, 4, d, 65536, d, d, None) == qhfpe.EINVAL
+    # one sample spans no interval of the trapezoid rule
+    assert L.qhfpe_spectrum_abs(d, 1, 0.1, d, 4, d, None) == qhfpe.EINVAL
+    assert L.qhfpe_spectrum_corr(d, 1, 4, 0.1, 0.1, d, 4, d, 4, d, d, None) == qhfpe.EINVAL
+    assert L.qhfpe_spectrum_corr(d, 4, 1, 0.1, 0.1, d, 4, d, 4, d, d, None) == qhfpe.EINVAL
 
 
 def test_null_arguments_rejected_without_gpu():

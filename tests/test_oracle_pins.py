@@ -603,3 +603,14 @@ def test_correlation_spectrum_separable():
     G1 = lambda w: (0.4 - 1j * w) / ((0.4 - 1j * w) ** 2 + 4.0)   # int e^{i w t} e^{-a t} cos(2t)
     exact = (F3[:, None] * (G1(w1) + G1(-w1))[None, :]).imag
     np.testing.assert_allclose(I, exact, rtol=2e-3, atol=2e-4)
+
+
+def test_spectra_need_two_samples():
+    """One sample spans no interval of the trapezoid rule: rejected."""
+    om = np.array([1.0, 2.0])
+    with pytest.raises(ValueError):
+        O.absorption_spectrum(np.ones(1, dtype=np.complex128), 0.1, om)
+    with pytest.raises(ValueError):
+        O.correlation_spectrum(np.ones((1, 5)), 0.1, 0.1, om, om)
+    with pytest.raises(ValueError):
+        O.correlation_spectrum(np.ones((5, 1)), 0.1, 0.1, om, om)
