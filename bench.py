@@ -78,9 +78,38 @@ def cpu_baseline(model: dict, nsteps: int = 30):
             O.trace_mu(m, W)
         dt = time.perf_counter() - t0
     cells = (m.depth + 1) * m.nq * m.np_
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=nsteps * cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                host_cpus=os.cpu_count(), cpu_model=cpu_model,
                 sample=f"{nsteps} RK4 steps (+trace) of the 256x256 depth-8 two-state hierarchy, "
                        f"zeta=1.0, FP64 NumPy, 1 thread, {dt:.1f} s")
+
+
+def copy_bandwidth_gbs(stream, nbytes: int = 1 << 30, reps: int = 20) -> float:
+    """Achieved bandwidth of a plain 1 GiB device copy (torch copy_), bytes
+    read plus bytes written per second: the practical HBM ceiling next to
+    the 8 TB/s peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=stream.device).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 10):
@@ -145,6 +174,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     omegas = torch.linspace(0.0, 20.0, 2001, dtype=torch.float64, device=dev)
+    copy_gbs = copy_bandwidth_gbs(stream)
 
     def run_leg(precision: str, steps: int, warmup: int):
         # both bath strengths run as one batch of independent members
@@ -200,6 +230,7 @@ def main():
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
+                    copy_peak_gbs=round(copy_gbs, 1), frac_of_copy_peak=round(achieved / copy_gbs, 4),
                     avg_stage_pass_us=round(launch_s * 1e6, 3), bytes_per_stage_pass=bytes_per_pass,
                     member_groups=groups, tile_variant=tile,
                     kernel_source_sha=kernel_source_sha())
