@@ -24,3 +24,12 @@ def single_state(poly1d, **kw):
                 mass=1.0, hbar=1.0, low_temp_correction=True)
     base.update(kw)
     return base
+
+
+def top_window(d: dict, k: int) -> dict:
+    """The model on the top k q columns of d's grid: same spacing, same upper
+    end, q_min moved up by nq - k columns."""
+    dq = (d["q_max"] - d["q_min"]) / d["nq"]
+    out = dict(d)
+    out.update(nq=k, q_min=d["q_min"] + (d["nq"] - k) * dq)
+    return out

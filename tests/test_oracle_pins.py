@@ -614,3 +614,33 @@ def test_spectra_need_two_samples():
         O.correlation_spectrum(np.ones((1, 5)), 0.1, 0.1, om, om)
     with pytest.raises(ValueError):
         O.correlation_spectrum(np.ones((5, 1)), 0.1, 0.1, om, om)
+
+
+def test_rhs_near_the_top_edge_needs_only_the_top_columns():
+    """Locality in q: the kinetic stencil reaches three columns and the
+    potential term at column i reads only that column, with U at
+    clamp(q_i +- r/2).  A state supported on the top S columns therefore has
+    the same RHS on the grid of the top K columns, once K dq covers the
+    support plus r_max / 2 = pi hbar / (2 dp); with too few columns the
+    clamp of U(q - r/2) differs.  (The GPU test at the largest level size
+    compares against the oracle on such a window.)"""
+    from helpers import top_window
+    nq, np_, S = 1500, 64, 32
+    d = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], nq=nq, np=np_, depth=1, q_min=0.0, q_max=30.0,
+                          p_min=-8.0, p_max=8.0)
+    dq, dp = 30.0 / nq, 16.0 / np_
+    K = S + int(np.ceil(np.pi / (2 * dp) / dq)) + 8
+    W = np.zeros((2, 2, 2, nq, np_), dtype=np.complex128)
+    W[..., nq - S:, :] = inputs.random_hierarchy(1, 2, S, np_, seed=5)
+    qt = (nq - 1) * dq
+    mg = O.paper_surfaces(D0=3.0, D1=2.5, a0=0.3, a1=0.4, q0=qt - 0.3, q1=qt - 0.15, dE=0.7, dV=0.45,
+                          qs=qt - 0.2, sigma=0.2)
+    for fn in (None, mg):
+        full, top, short = oracle_model(d), oracle_model(top_window(d, K)), oracle_model(top_window(d, S + 10))
+        full.potential_fn = top.potential_fn = short.potential_fn = fn
+        F = O.rhs(full, W)
+        assert not np.any(F[..., : nq - K, :])
+        Ft = O.rhs(top, W[..., nq - K:, :])
+        assert np.linalg.norm(Ft - F[..., nq - K:, :]) < 1e-13 * np.linalg.norm(F)
+        Fs = O.rhs(short, W[..., nq - S - 10:, :])
+        assert np.linalg.norm(Fs - F[..., nq - S - 10:, :]) > 1e-6 * np.linalg.norm(F)
