@@ -90,6 +90,11 @@ def cpu_baseline(model: dict, nsteps: int = 30):
                        f"zeta=1.0, FP64 NumPy, 1 thread, {dt:.1f} s")
 
 
+def note(msg: str):
+    """A progress line on stderr as each part of the run finishes."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def copy_bandwidth_gbs(stream, nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Achieved bandwidth of a plain 1 GiB device copy (torch copy_), bytes
     read plus bytes written per second: the practical HBM ceiling next to
@@ -150,6 +155,9 @@ def main():
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
                          "a quarter three-state, 5000 steps, FP32 state)")
     ap.add_argument("--sweep-steps", type=int, default=0, help="steps of the sweep (0: the workload's 5000)")
+    ap.add_argument("--fp64-check", action="store_true",
+                    help="with --two-d / --sweep: rerun with the FP64 state (untimed) and report the FP32 "
+                         "spectra's error against it")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -240,6 +248,7 @@ def main():
         return out
 
     main_leg = run_leg(args.precision, args.steps, args.warmup)
+    note(f"{args.precision} leg: {main_leg['ms_per_step']:.1f} ms per step")
     line = {
         "metric": "hierarchy cell-updates/s",
         "value": main_leg["value"],
@@ -268,12 +277,13 @@ def main():
         errs = []
         for s32, s64 in zip(leg["spec"], main_leg["spec"]):
             errs.append(float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64))))
+        note(f"fp32 leg: {leg['ms_per_step']:.1f} ms per step")
         line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
     if args.two_d:
-        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale)
+        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, args.fp64_check)
     if args.sweep:
-        line["uneven_sweep"] = uneven_sweep(args.sweep_steps, args.sweep_streams)
+        line["uneven_sweep"] = uneven_sweep(args.sweep_steps, args.sweep_streams, args.fp64_check)
     if args.paper:
         line["paper_workload"] = paper_workload(args.paper_steps)
     if not args.no_cpu_baseline:
@@ -282,11 +292,12 @@ def main():
     print(json.dumps(line, default=float))
 
 
-def uneven_sweep(nsteps: int = 0, streams: int = 1):
+def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
     """Wall time of the uneven batched sweep: plan (spectral radius and
     substeps per member, reported apart), then all members as batches of
     like-shaped members on concurrent streams (`streams` at a time), FP32 state,
-    R1 every step."""
+    R1 every step.  fp64_check: run the sweep again with the FP64 state
+    (untimed) and report the largest error of the FP32 absorption spectra."""
     import numpy as np
     import torch
 
@@ -302,11 +313,23 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1):
     R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=streams, batches=batches)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return dict(wall_s=t2 - t1, plan_s=t1 - t0, members=len(members), batches=len(batches), rk4_steps=nsteps,
-                batch_streams=streams,
-                substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
-                cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
-                finite=bool(all(np.all(np.isfinite(r)) for r in R)))
+    out = dict(wall_s=t2 - t1, plan_s=t1 - t0, members=len(members), batches=len(batches), rk4_steps=nsteps,
+               batch_streams=streams,
+               substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
+               cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
+               finite=bool(all(np.all(np.isfinite(r)) for r in R)))
+    note(f"sweep: FP32 run {t2 - t1:.1f} s")
+    if fp64_check:
+        from paper_1706_09590_amd import qhfpe
+        R64, _ = sweep.run_sweep(members, nsteps, w["dt"], precision="fp64", streams=streams, batches=batches)
+        om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
+        errs = []
+        for r32, r64 in zip(R, R64):
+            i32 = qhfpe.spectrum_abs(torch.from_numpy(r32), w["dt"], om).cpu().numpy()
+            i64 = qhfpe.spectrum_abs(torch.from_numpy(r64), w["dt"], om).cpu().numpy()
+            errs.append(float(np.max(np.abs(i32 - i64)) / np.max(np.abs(i64))))
+        out["fp32_spectrum_max_rel_err_vs_fp64"] = max(errs)
+    return out
 
 
 def paper_workload(nsteps: int = 0):
@@ -372,7 +395,7 @@ def paper_workload(nsteps: int = 0):
     return out
 
 
-def two_d_spectrum(scale: int = 1):
+def two_d_spectrum(scale: int = 1, fp64_check: bool = False):
     """Wall time of the batched 2D correlation spectrum: FP64 equilibration of
     the 128x128 depth-6 hierarchy (reported apart), then t1 / t2 preparation
     and all t3 propagations as one batch (FP32 state, FP64 traces), and the
@@ -392,6 +415,7 @@ def two_d_spectrum(scale: int = 1):
     W_eq, steps, res = response.equilibrate(m, tol=1e-10, max_steps=100000, check_every=500, dt=dt_relax)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    note(f"2D spectrum: equilibrated in {steps} steps")
     R3 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp32")
     om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
     dt = m["dt"]
@@ -402,9 +426,18 @@ def two_d_spectrum(scale: int = 1):
     cells = (m["depth"] + 1) * m["nq"] * m["np"]
     prep = sum(t1s[-1:]) + len(t1s) * t2s[-1]
     updates = cells * (len(t1s) * len(t2s) * w["n3_steps"] + prep)
-    return dict(wall_s=t2 - t1, equilibration_s=t1 - t0, equilibration_steps=steps, equilibration_residual=res,
-                n_t1=len(t1s), n_t2=len(t2s), n3_steps=w["n3_steps"], cell_updates=updates,
-                cell_updates_per_s=updates / (t2 - t1), finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
+    out = dict(wall_s=t2 - t1, equilibration_s=t1 - t0, equilibration_steps=steps, equilibration_residual=res,
+               n_t1=len(t1s), n_t2=len(t2s), n3_steps=w["n3_steps"], cell_updates=updates,
+               cell_updates_per_s=updates / (t2 - t1), finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
+    note(f"2D spectrum: FP32 run {t2 - t1:.1f} s")
+    if fp64_check:
+        # the same spectra from the FP64 state (untimed): the FP32 error statement
+        R64 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp64")
+        Ic64 = response.correlation_spectra(R64, (t1s[1] - t1s[0]) * dt, w["stride3"] * dt, om, om)
+        It64 = response.transient_absorption(R64, w["stride3"] * dt, om)
+        out["fp32_corr_max_rel_err_vs_fp64"] = float((Ic - Ic64).abs().max() / Ic64.abs().max())
+        out["fp32_tas_max_rel_err_vs_fp64"] = float((It - It64).abs().max() / It64.abs().max())
+    return out
 
 
 if __name__ == "__main__":

@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import oracle_model
+from helpers import oracle_model, top_window
 from oracle import qhfpe_oracle as O
 from paper_1706_09590_amd import inputs
 
@@ -301,3 +301,52 @@ def test_copy_members_within_a_handle_and_across_streams():
     np.testing.assert_array_equal(got, R.get_state().cpu().numpy()[0])
     for h in (A, B, R):
         h.close()
+
+
+def test_largest_level_size_rhs_parity():
+    """One level just under the 2 GiB that 32-bit byte offsets address
+    (two states, np = 256, nq = 262143, FP64: 2 GiB - 8 KiB; two levels).
+    The state is supported on the top 64 q columns, so the last columns,
+    the highest byte offsets and the ghost columns past the upper q edge are
+    in play.  The oracle computes the RHS on the top 1400 columns, which
+    reproduces the full grid's RHS there (pinned on the CPU by
+    test_rhs_near_the_top_edge_needs_only_the_top_columns); every column
+    below must come out exactly zero.  Quartic surfaces with a constant
+    coupling in both stage variants, then Morse/Gaussian surfaces (a
+    q-dependent coupling, wave variant)."""
+    nq, np_, S, K = 262143, 256, 64, 1400
+    d = small_model(ns=2, nq=nq, np_=np_, depth=1, q_min=0.0, q_max=nq * 0.02, p_min=-8.0, p_max=8.0)
+    assert 4 * nq * np_ * 8 < 2 ** 31
+    assert K * 0.02 > np.pi / (2 * 16.0 / np_) + S * 0.02
+    qt = (nq - 1) * 0.02
+    mg = dict(D0=3.0, D1=2.5, a0=0.05, a1=0.06, q0=qt - 1.0, q1=qt - 0.5, dE=0.7, dV=0.45, qs=qt - 0.7,
+              sigma=0.5)
+    blob = inputs.random_hierarchy(1, 2, S, np_, seed=77)
+    say("largest level: building the state")
+    W = torch.zeros((1, 2, 2, 2, nq, np_), dtype=torch.complex128, device="cuda")
+    W[0, ..., nq - S:, :] = torch.from_numpy(blob).cuda()
+    Wtop = np.zeros((2, 2, 2, K, np_), dtype=np.complex128)
+    Wtop[..., K - S:, :] = blob
+    P = qhfpe.Propagator(d, batch=1, precision="fp64")
+    try:
+        for case, tile in (("quartic", 1), ("quartic", 4), ("morse-gauss", 1)):
+            say(f"largest level: {case}, tile {tile}")
+            if case == "morse-gauss":
+                P.set_potential_morse_gauss(**mg)
+            P.set_tile(tile)
+            P.set_state(W, phase=0)
+            P.apply_rhs()
+            out = P.get_state()
+            assert not bool(out[0, ..., : nq - K, :].any())
+            got = out[0, ..., nq - K:, :].cpu().numpy()
+            del out
+            m = oracle_model(top_window(d, K))
+            if case == "morse-gauss":
+                m.potential_fn = O.paper_surfaces(**mg)
+            err = rel(got, O.rhs(m, Wtop))
+            say(f"  relative error {err:.3e}")
+            assert err < 1e-12, (case, tile, err)
+    finally:
+        P.close()
+        del W
+        torch.cuda.empty_cache()
