@@ -150,10 +150,42 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
     return results, info
 
 
+def amplification(members, nsteps: int, dt: float, batches=None, seed: int = 11, precision: str = "fp64",
+                  device=None) -> np.ndarray:
+    """||W(2t)|| / ||W(t)|| per member, with t = nsteps steps of dt (and the
+    members' substeps), from a seeded random hierarchy that excites every
+    mode.  The first half lets the transient growth of non-normal modes
+    pass; a ratio far above 1 then marks a member whose discretized operator
+    has eigenvalues with positive real part (deep hierarchies with strong,
+    cold baths on these grids): its response grows and amplifies rounding.
+    batches: from plan() (computed here if None)."""
+    import torch
+    if batches is None:
+        _, batches = plan(members, dt, device=device)
+    amp = np.zeros(len(members))
+    for mod, ids, subs in batches:
+        P = qhfpe.Propagator(inputs.model_dict(mod, dt=dt / subs), batch=len(ids), precision=precision,
+                             device=device)
+        try:
+            for j, i in enumerate(ids):
+                m = members[i]
+                P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
+            W = inputs.random_hierarchy(mod["depth"], mod["n_states"], mod["nq"], mod["np"], seed=seed,
+                                        smooth=False)
+            P.set_state(torch.from_numpy(np.broadcast_to(W, (len(ids),) + W.shape).copy()), phase=0)
+            P.step(nsteps * subs, 1, record=False)
+            n1 = P.residual()[:, 1]
+            P.step(nsteps * subs, 1, record=False)
+            amp[ids] = P.residual()[:, 1] / n1
+        finally:
+            P.close()
+    return amp
+
+
 def sweep_cell_updates(members, nsteps: int, substeps) -> int:
     """Cell-updates (one cell of every level, all components, one RK4 step) of a sweep."""
     return int(sum((m["depth"] + 1) * m["grid"] ** 2 * nsteps * int(s) for m, s in zip(members, substeps)))
 
 
-__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "run_sweep", "sweep_cell_updates",
-           "RK4_MARGIN"]
+__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "run_sweep", "amplification",
+           "sweep_cell_updates", "RK4_MARGIN"]

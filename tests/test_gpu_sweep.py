@@ -103,3 +103,24 @@ def test_full_sweep_sampled_members():
         ref = (1j / m.hbar) * tr
         err = np.linalg.norm(R[i] - ref) / np.linalg.norm(ref)
         assert err < 1e-4, (i, err)
+
+
+def test_amplification_matches_the_oracle():
+    """sweep.amplification (the library's FP64 propagation from a seeded
+    random hierarchy, norm growth over the second of two equal spans)
+    against the oracle's: a strongly damped deep member that grows and a
+    weakly damped one that decays."""
+    members = [dict(grid=24, depth=6, n_states=2, zeta=4.0, gamma=1.0, beta=2.9),
+               dict(grid=24, depth=2, n_states=2, zeta=0.5, gamma=1.0, beta=1.0)]
+    dt, nsteps = 0.002, 100
+    subs, batches = sweep.plan(members, dt)
+    say(f"amplification, substeps {list(subs)}")
+    amp = sweep.amplification(members, nsteps, dt, batches=batches)
+    for i, mem in enumerate(members):
+        m = oracle_model(inputs.model_dict(sweep.member_model(mem, dt), dt=dt / subs[i]))
+        W = inputs.random_hierarchy(mem["depth"], 2, mem["grid"], mem["grid"], seed=11, smooth=False)
+        W1, _ = O.propagate(m, W, nsteps * int(subs[i]), nsteps, record=False)
+        W2, _ = O.propagate(m, W1, nsteps * int(subs[i]), nsteps, record=False)
+        ref = np.linalg.norm(W2) / np.linalg.norm(W1)
+        assert amp[i] == pytest.approx(ref, rel=1e-9), (i, amp[i], ref)
+    assert amp[0] > 5.0 and amp[1] < 1.0

@@ -644,3 +644,26 @@ def test_rhs_near_the_top_edge_needs_only_the_top_columns():
         assert np.linalg.norm(Ft - F[..., nq - K:, :]) < 1e-13 * np.linalg.norm(F)
         Fs = O.rhs(short, W[..., nq - S - 10:, :])
         assert np.linalg.norm(Fs - F[..., nq - S - 10:, :]) > 1e-6 * np.linalg.norm(F)
+
+
+def test_deep_hierarchy_with_a_strong_cold_bath_grows():
+    """A property of the discretized operator under these readings (fifth-
+    order upwind D_q with zero ghost columns, periodic D_p, the Eq. (GMFP)
+    terminator at n = N), not of the continuous equations: with a strong,
+    cold bath (zeta = 4, beta = 2.9) the depth-6 hierarchy on a 24 x 24 grid
+    has growing modes (they sit on the terminator level near a q edge), so a
+    random state is amplified ~1000x in 100 steps, while the depth-2
+    hierarchy, or a weak bath at depth 6, stays bounded.  The uneven sweep's
+    strongly damped deep members show this growth (in both precisions)."""
+    from paper_1706_09590_amd import sweep
+
+    def amp(depth, zeta, beta):
+        mem = dict(grid=24, depth=depth, n_states=2, zeta=zeta, gamma=1.0, beta=beta)
+        m = oracle_model(sweep.member_model(mem, 0.002))
+        W = inputs.random_hierarchy(depth, 2, 24, 24, seed=11, smooth=False)
+        Wt, _ = O.propagate(m, W, 100, 100, record=False)
+        return np.linalg.norm(Wt) / np.linalg.norm(W)
+
+    assert amp(6, 4.0, 2.9) > 100.0
+    assert amp(2, 4.0, 2.9) < 10.0
+    assert amp(6, 0.5, 1.0) < 1.0
