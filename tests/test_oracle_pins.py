@@ -647,11 +647,11 @@ def test_rhs_near_the_top_edge_needs_only_the_top_columns():
 
 
 def test_deep_hierarchy_with_a_strong_cold_bath_grows():
-    """A property of the discretized operator under these readings (fifth-
-    order upwind D_q with zero ghost columns, periodic D_p, the Eq. (GMFP)
-    terminator at n = N), not of the continuous equations: with a strong,
-    cold bath (zeta = 4, beta = 2.9) the depth-6 hierarchy on a 24 x 24 grid
-    has growing modes (they sit on the terminator level near a q edge), so a
+    """A property of the truncated hierarchy (Eq. (heom) closed by Eq.
+    (GMFP)) at strong damping, present even without the kinetic and
+    potential terms: the level couplings n gamma zeta p grow with |p|, and
+    with a strong, cold bath (zeta = 4, beta = 2.9) the depth-6 hierarchy
+    on a 24 x 24 grid has growing modes (on the terminator level), so a
     random state is amplified ~1000x in 100 steps, while the depth-2
     hierarchy, or a weak bath at depth 6, stays bounded.  The uneven sweep's
     strongly damped deep members show this growth (in both precisions)."""
