@@ -141,3 +141,30 @@ def test_default_rule_and_limits():
             with pytest.raises(qhfpe.QHFPEError):
                 P.set_streams(bad)
         P.close()
+
+
+def test_binding_orders_the_handle_stream_against_torch():
+    """A handle on its own stream, driven from torch's default stream: the
+    state handed in is produced by a torch kernel just before (the handle's
+    stream must wait for it), and the state read back after an asynchronous
+    operator application is consumed by torch at once (torch must wait for
+    the handle's stream).  Both must match a run on one stream."""
+    say("binding stream ordering")
+    d = model(nq=20, np_=128, depth=2)
+    W = inputs.random_hierarchy(2, 2, 20, 128, seed=5)
+    Wd = torch.from_numpy(W[None]).cuda()
+
+    def run(stream):
+        P = qhfpe.Propagator(d, batch=1, precision="fp64", stream=stream)
+        try:
+            src = Wd * 2.0  # a torch kernel on the current stream
+            P.set_state(src)
+            for _ in range(3):
+                P.apply_rhs()  # asynchronous on the handle's stream
+            return (P.get_state() * 1.0).cpu().numpy()  # consumed by torch right away
+        finally:
+            P.close()
+
+    ref = run(None)
+    got = run(torch.cuda.Stream())
+    assert np.array_equal(got, ref)
