@@ -200,7 +200,10 @@ int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise);
  * Advances the phase by one. */
 int qhfpe_apply_dipole(qhfpe_t* h, int32_t mode);
 
-/* Advance nsteps RK4 steps of dt (Sec. II, Eqs. (heom), (GMFP)).
+/* Advance nsteps RK4 steps of dt (Sec. II, Eqs. (heom), (GMFP)).  Each
+ * step applies the classical RK4 polynomial in dt L as the product of its
+ * two real quadratic factors (four stage launches; equal to Kutta's form
+ * up to rounding).
  * If d_resp != NULL it receives, per member, the complex FP64 trace
  * Tr{mu W^(0)} (including i^phase) at t = 0 and after every stride steps:
  * d_resp[B][nsteps/stride + 1][2]; nsteps must be a multiple of stride.
