@@ -137,3 +137,46 @@ def brownian_moments(Omega, mass, zeta, gamma, c0, cdelta):
     q2, _ = integrate.quad(lambda w: chi2(w) * spec(w), 0.0, np.inf, limit=400, epsabs=1e-13, epsrel=1e-12)
     p2, _ = integrate.quad(lambda w: w * w * chi2(w) * spec(w), 0.0, np.inf, limit=400, epsabs=1e-13, epsrel=1e-12)
     return q2 / np.pi, mass ** 2 * p2 / np.pi
+
+
+def displaced_oscillator_R3_basis(t1, t2, t3, d, E, Omega, beta, mu=1.0, nbasis=60, mass=1.0, hbar=1.0):
+    """Third-order response of Sec. III, Eq. (R3), by brute force for two
+    undamped displaced harmonic surfaces with a Condon dipole:
+
+        R3(t3, t2, t1) = (i/hbar)^3 Tr{ mu G(t3) mu^x G(t2) mu^x G(t1) mu^x rho_eq },
+
+    with G(t) A = exp(-i H t/hbar) A exp(+i H t/hbar), mu^x A = mu A - A mu and
+    rho_eq = |g><g| (x) exp(-beta H_g)/Z, all written out as matrices in a
+    truncated oscillator basis of each electronic state (no Wigner function,
+    no grid, no cumulant).  H_g = p^2/2m + m W^2 q^2/2,
+    H_e = p^2/2m + m W^2 (q-d)^2/2 + E.  t1, t2, t3: 1-D arrays.  Returns
+    R3[len(t2)][len(t1)][len(t3)] (complex; real up to rounding)."""
+    n = np.arange(nbasis)
+    a = np.diag(np.sqrt(n[1:]), 1)
+    x = np.sqrt(hbar / (2.0 * mass * Omega)) * (a + a.T)
+    Hg = np.diag(hbar * Omega * (n + 0.5))
+    He = Hg - mass * Omega ** 2 * d * x + (0.5 * mass * Omega ** 2 * d * d + E) * np.eye(nbasis)
+    Z = np.zeros((nbasis, nbasis))
+    H = np.block([[Hg, Z], [Z, He]])
+    ev, V = np.linalg.eigh(H)
+    I = np.eye(nbasis)
+    M = mu * np.block([[Z, I], [I, Z]])
+    rg = np.diag(np.exp(-beta * np.diag(Hg)))
+    rho = np.block([[rg / np.trace(rg), Z], [Z, Z]]).astype(np.complex128)
+
+    def G(t, A):
+        U = V @ np.diag(np.exp(-1j * ev * t / hbar)) @ V.conj().T
+        return U @ A @ U.conj().T
+
+    def mux(A):
+        return M @ A - A @ M
+
+    pref = (1j / hbar) ** 3
+    out = np.zeros((len(t2), len(t1), len(t3)), dtype=np.complex128)
+    for i1, s1 in enumerate(t1):
+        X = mux(G(s1, mux(rho)))
+        for i2, s2 in enumerate(t2):
+            Y = mux(G(s2, X))
+            for i3, s3 in enumerate(t3):
+                out[i2, i1, i3] = pref * np.trace(M @ G(s3, Y))
+    return out

@@ -9,8 +9,12 @@ Calls only oracle/ (and the seeded inputs).  Outputs (NumPy .npz, no pickles):
   production_100.npz          256x256, depth 8, zeta in {0.1, 1.0}: thermal
                               state, mu^x, 100 RK4 steps of 0.002: trace series
                               and sampled q columns of levels 0 and 8.
+  production_2000.npz         the same for 2000 RK4 steps (t = 4): the trace at
+                              every step and the sampled columns at the end
+                              (about 20 CPU-minutes per zeta; the two zeta run
+                              in two processes).
 
-Usage: python tests/golden/make_oracle_refs.py [small|production|all]
+Usage: python tests/golden/make_oracle_refs.py [small|production|production2000|all]
 """
 
 import os
@@ -46,18 +50,30 @@ def small():
     print(f"small: {time.time() - t0:.1f} s")
 
 
-def production(nsteps=100):
+def production_member(z, nsteps):
+    """One bath strength of the production workload: trace series and the
+    sampled columns of the first and last level after nsteps steps."""
+    w = inputs.PRODUCTION_ABSORPTION
+    m = oracle_model(inputs.model_dict(w["model"], zeta=z))
+    W = O.dipole_commutator(m, O.thermal_initial_state(m, w["thermal_omega"]))
+    t0 = time.time()
+    W, tr = O.propagate(m, W, nsteps, 1)
+    print(f"production zeta={z}, {nsteps} steps: {time.time() - t0:.1f} s", flush=True)
+    return {f"trace_zeta{z}": tr, f"level0_zeta{z}": W[0][:, :, PRODUCTION_COLUMNS, :],
+            f"level_last_zeta{z}": W[-1][:, :, PRODUCTION_COLUMNS, :]}
+
+
+def production(nsteps=100, processes=1):
     w = inputs.PRODUCTION_ABSORPTION
     out = {}
-    for z in w["zetas"]:
-        m = oracle_model(inputs.model_dict(w["model"], zeta=z))
-        W = O.dipole_commutator(m, O.thermal_initial_state(m, w["thermal_omega"]))
-        t0 = time.time()
-        W, tr = O.propagate(m, W, nsteps, 1)
-        out[f"trace_zeta{z}"] = tr
-        out[f"level0_zeta{z}"] = W[0][:, :, PRODUCTION_COLUMNS, :]
-        out[f"level_last_zeta{z}"] = W[-1][:, :, PRODUCTION_COLUMNS, :]
-        print(f"production zeta={z}: {time.time() - t0:.1f} s")
+    if processes > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=processes) as ex:
+            for part in ex.map(production_member, w["zetas"], [nsteps] * len(w["zetas"])):
+                out.update(part)
+    else:
+        for z in w["zetas"]:
+            out.update(production_member(z, nsteps))
     np.savez_compressed(os.path.join(HERE, f"production_{nsteps}.npz"), columns=np.array(PRODUCTION_COLUMNS),
                         **out)
 
@@ -68,3 +84,5 @@ if __name__ == "__main__":
         small()
     if what in ("production", "all"):
         production()
+    if what in ("production2000", "all"):
+        production(2000, processes=2)

@@ -548,6 +548,45 @@ def test_displaced_oscillator_linear_response():
     assert np.max(np.abs(R1.imag)) < 1e-12
 
 
+def test_displaced_oscillator_third_order_response():
+    """Sec. III, Eq. (R3): the oracle's multi-time protocol (mu^x, G(t1),
+    mu^x, G(t2), mu^x, G(t3), trace with mu, and the (i/hbar)^3 factor) on
+    undamped displaced harmonic surfaces from the exact thermal state,
+    against the same expression evaluated with matrices in a truncated
+    oscillator basis.  Unequal t1 and t2 grids: a swapped axis, a sign of
+    the prefactor, or a commutator applied at the wrong time changes R3 by
+    O(1) (max |R3| = 7 here); the grid-limited agreement is 2e-5."""
+    dshift, E = 1.0, 3.0
+    a = [0.0, 0.0, 0.5, 0, 0]
+    b = [0.5 * dshift ** 2 + E, -dshift, 0.5, 0, 0]
+    d = dict(n_states=2, nq=64, np=48, q_min=-8.0, q_max=10.0, p_min=-8.0, p_max=8.0,
+             depth=0, zeta=0.0, gamma=1.0, beta=1.0, dt=0.01,
+             poly=[[a, [0] * 5], [[0] * 5, b]], mu=[[0, 1], [1, 0]])
+    m = oracle_model(d)
+    t1_steps, t2_steps, n3, stride = [0, 30, 80], [0, 60], 160, 16
+    R3 = O.third_order_response(m, O.thermal_initial_state(m, 1.0), t1_steps, t2_steps, n3, stride)
+    ref = cf.displaced_oscillator_R3_basis(np.array(t1_steps) * m.dt, np.array(t2_steps) * m.dt,
+                                           np.arange(n3 // stride + 1) * stride * m.dt, dshift, E, 1.0, 1.0)
+    assert R3.shape == ref.shape
+    assert np.max(np.abs(ref)) > 5.0
+    assert np.max(np.abs(R3 - ref)) < 1e-4
+    assert np.max(np.abs(R3.imag)) < 1e-12
+
+
+def test_oscillator_basis_response_is_converged_and_real():
+    """The brute-force R3 reference itself: converged in the basis size and
+    real, as Eq. (R3) requires for a Hermitian equilibrium state."""
+    t = np.array([0.0, 0.4, 1.1])
+    r60 = cf.displaced_oscillator_R3_basis(t, t[:2], t, 1.0, 3.0, 1.0, 1.0, nbasis=60)
+    r90 = cf.displaced_oscillator_R3_basis(t, t[:2], t, 1.0, 3.0, 1.0, 1.0, nbasis=90)
+    assert np.max(np.abs(r60 - r90)) < 1e-12
+    assert np.max(np.abs(r60.imag)) < 1e-12
+    # at t3 = 0 the last commutator's trace with mu vanishes by cyclicity,
+    # Tr{mu [mu, X]} = 0, for every t1, t2
+    assert np.max(np.abs(r60[:, :, 0])) < 1e-12
+    assert np.max(np.abs(r60[:, :, 1:])) > 1.0
+
+
 @pytest.mark.slow
 def test_brownian_oscillator_equilibrium_moments():
     """Harmonic system, full hierarchy with the low-temperature correction:
