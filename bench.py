@@ -7,7 +7,13 @@ hierarchy with Tr{mu W^(0)} sampled every step (FP64 reductions), and the
 absorption spectrum on omega in [0, 20] (2001 points).  Inputs are resident
 in HBM before the timed region; the handles are created beforehand.
 
-Prints one JSON line (metric: hierarchy cell-updates per second).
+The same line carries the batched 2D spectrum (128 x 128, depth 6, 64 x 16
+delays, 1024 t3 propagations of 4000 steps, FP32 state): its wall time
+(equilibration reported apart), the roofline of its t3 stage launch and the
+error of its FP32 spectra against the FP64-state run.
+
+Prints one JSON line (metric: hierarchy cell-updates per second and the 2D
+spectrum wall time).
 """
 
 from __future__ import annotations
@@ -60,12 +66,15 @@ def read_traffic(precision: str):
         return None
 
 
-def cpu_baseline(model: dict, nsteps: int = 30):
-    """The FP64 oracle, single-threaded, on a bounded sample: `nsteps` RK4
-    steps of the same 256 x 256 depth-8 hierarchy (zeta = 1.0)."""
+def _oracle_propagation(args):
+    """One independent propagation of the oracle (a pool worker): `nsteps`
+    RK4 steps plus the trace per step, single-threaded.  Returns
+    (cell-updates, seconds)."""
+    model, nsteps = args
     for v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
         os.environ[v] = "1"
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import qhfpe_oracle as O
     m = O.Model(n_states=model["n_states"], nq=model["nq"], np_=model["np"], q_min=model["q_min"],
@@ -75,7 +84,6 @@ def cpu_baseline(model: dict, nsteps: int = 30):
     W = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
     tables = O.moyal_tables(m)
     # numpy may already be loaded with threaded BLAS pools: limit them here
-    from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         W = O.rk4_step(m, W, tables=tables)  # warm caches
         t0 = time.perf_counter()
@@ -83,17 +91,51 @@ def cpu_baseline(model: dict, nsteps: int = 30):
             W = O.rk4_step(m, W, tables=tables)
             O.trace_mu(m, W)
         dt = time.perf_counter() - t0
-    cells = (m.depth + 1) * m.nq * m.np_
+    return nsteps * (m.depth + 1) * m.nq * m.np_, dt
+
+
+def host_cores() -> int:
+    """CPUs this process may run on, at most 16 (the GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(models: list, nsteps_single: int = 24, nsteps_pool: int = 12):
+    """The FP64 oracle on bounded samples of the same workload (the 256 x 256
+    depth-8 hierarchy): one propagation of `nsteps_single` RK4 steps on one
+    core, then one propagation per host core (the two bath strengths in
+    turn) of `nsteps_pool` steps each in a process pool, every process
+    single-threaded.  The pool figure is the pool's cell-updates over the
+    longest timed loop of its workers (they run at the same time; process
+    start and table setup are not timed, as in the one-core figure);
+    `cores` is the pool size."""
+    from concurrent.futures import ProcessPoolExecutor
+    upd, t1 = _oracle_propagation((models[-1], nsteps_single))
+    single = dict(value=upd / t1, unit="cell-updates/s", cores=1,
+                  sample=f"{nsteps_single} RK4 steps (+trace), zeta={models[-1]['zeta']}, {t1:.1f} s")
+    ncores = host_cores()
+    jobs = [(models[k % len(models)], nsteps_pool) for k in range(ncores)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=ncores) as ex:
+        res = list(ex.map(_oracle_propagation, jobs))
+    wall = time.perf_counter() - t0
+    total = sum(u for u, _ in res)
+    slowest = max(t for _, t in res)
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as f:
             cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=nsteps * cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                host_cpus=os.cpu_count(), cpu_model=cpu_model,
-                sample=f"{nsteps} RK4 steps (+trace) of the 256x256 depth-8 two-state hierarchy, "
-                       f"zeta=1.0, FP64 NumPy, 1 thread, {dt:.1f} s")
+    return dict(value=total / slowest, unit="cell-updates/s", cores=ncores, kind="oracle",
+                host_cpus=os.cpu_count(), cpu_model=cpu_model, single_core=single,
+                sample=f"{ncores} independent propagations of {nsteps_pool} RK4 steps (+trace) of the 256x256 "
+                       f"depth-8 two-state hierarchy (zeta alternating over {[m['zeta'] for m in models]}), "
+                       f"FP64 NumPy, one single-threaded process per core; slowest worker {slowest:.1f} s, "
+                       f"pool wall {wall:.1f} s including process start and table setup")
 
 
 def note(msg: str):
@@ -101,37 +143,47 @@ def note(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def copy_bandwidth_gbs(stream, nbytes: int = 1 << 30, reps: int = 20) -> float:
-    """Achieved bandwidth of a plain 1 GiB device copy (torch copy_), bytes
-    read plus bytes written per second: the practical HBM ceiling next to
-    the 8 TB/s peak."""
+def copy_bandwidth_gbs(stream, nbytes: int = 1 << 30, reps: int = 20) -> dict:
+    """Achieved bandwidth of a plain 1 GiB device copy, bytes read plus bytes
+    written per second: the practical HBM ceiling next to the 8 TB/s peak.
+    `project`: the library's streaming copy kernel (qhfpe_stream_copy);
+    `torch`: torch's copy_, for comparison."""
     import torch
+
+    from paper_1706_09590_amd import qhfpe
     a = torch.empty(nbytes // 4, dtype=torch.float32, device=stream.device).fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    out = {}
+    for name, fn in (("project", lambda: qhfpe.stream_copy(b, a, stream=stream)), ("torch", lambda: b.copy_(a))):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    assert torch.equal(a, b)
     del a, b
     torch.cuda.empty_cache()
-    return gbs
+    return out
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 10):
-    """Plain device copy of a known size (for scaling the FETCH_SIZE/WRITE_SIZE counters)."""
+    """Plain device copy of a known size by the library's streaming kernel
+    (for scaling the FETCH_SIZE/WRITE_SIZE counters)."""
     import torch
+
+    from paper_1706_09590_amd import qhfpe
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(reps):
-        b.copy_(a)
+        qhfpe.stream_copy(b, a)
     torch.cuda.synchronize()
-    print(json.dumps(dict(copy_probe_bytes=nbytes, reps=reps)))
+    print(json.dumps(dict(copy_probe_bytes=nbytes, reps=reps, kernel="stream_copy_kernel")))
 
 
 def main():
@@ -149,8 +201,11 @@ def main():
     ap.add_argument("--groups", type=int, default=0,
                     help="member groups of each step on streams of their own (0 = library default)")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--two-d", action="store_true",
-                    help="also time the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
+    ap.add_argument("--no-two-d", action="store_true",
+                    help="skip the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
+    ap.add_argument("--two-d-graph", action="store_true",
+                    help="run the 2D spectrum's protocol as one recorded graph (record and instantiate "
+                         "reported apart)")
     ap.add_argument("--two-d-scale", type=int, default=1,
                     help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
     ap.add_argument("--paper", action="store_true",
@@ -162,8 +217,10 @@ def main():
                          "a quarter three-state, 5000 steps, FP32 state)")
     ap.add_argument("--sweep-steps", type=int, default=0, help="steps of the sweep (0: the workload's 5000)")
     ap.add_argument("--fp64-check", action="store_true",
-                    help="with --two-d / --sweep: rerun with the FP64 state (untimed) and report the FP32 "
-                         "spectra's error against it")
+                    help="with --sweep: rerun with the FP64 state (untimed) and report the FP32 spectra's "
+                         "error against it (the 2D spectrum always does)")
+    ap.add_argument("--no-fp64-check-2d", action="store_true",
+                    help="skip the untimed FP64-state rerun of the 2D spectrum")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -188,7 +245,8 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     omegas = torch.linspace(0.0, 20.0, 2001, dtype=torch.float64, device=dev)
-    copy_gbs = copy_bandwidth_gbs(stream)
+    copy = copy_bandwidth_gbs(stream)
+    copy_gbs = copy["project"]
 
     def run_leg(precision: str, steps: int, warmup: int):
         # both bath strengths run as one batch of independent members
@@ -235,18 +293,25 @@ def main():
         passes = steps * nsteps * 4
         w = 8 if precision == "fp64" else 4
         nc = base["n_states"] ** 2
-        # algorithmic bytes per RK4 step and cell (the step is the product of two
-        # quadratic factors): stages 1 and 3 read one array (as v and y) and write
-        # (2 passes each); stages 2 and 4 read v, read y and write (3 passes each)
-        bytes_per_pass = 10 * nc * w * cells * len(zetas) / 4.0
+        # algorithmic bytes per cell-update: 12 n_s^2 w (each of the four RK4
+        # stages reads v, reads y and writes v'), so 3 n_s^2 w per cell and
+        # stage pass
+        bytes_per_pass = 3 * nc * w * cells * len(zetas)
+        # the factored step moves fewer: stages 1 and 3 read one array (as v
+        # and y) and write, stages 2 and 4 read v, read y and write
+        bytes_per_pass_factored = 10 * nc * w * cells * len(zetas) / 4.0
         launch_s = gpu_s / passes
         achieved = bytes_per_pass / launch_s / 1e9
         traffic = read_traffic(precision)
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=(round(traffic / launch_s / 1e9, 1) if traffic else None),
-                    copy_peak_gbs=round(copy_gbs, 1), frac_of_copy_peak=round(achieved / copy_gbs, 4),
+                    copy_peak_gbs=round(copy_gbs, 1), torch_copy_gbs=round(copy["torch"], 1),
+                    frac_of_copy_peak=round(achieved / copy_gbs, 4),
                     avg_stage_pass_us=round(launch_s * 1e6, 3), bytes_per_stage_pass=bytes_per_pass,
+                    achieved_factored_bytes=round(bytes_per_pass_factored / launch_s / 1e9, 1),
+                    frac_factored_bytes=round(bytes_per_pass_factored / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                    bytes_per_stage_pass_factored=bytes_per_pass_factored,
                     member_groups=groups, tile_variant=tile,
                     kernel_source_sha=kernel_source_sha())
         out = dict(value=updates / wall, wall_s=wall, gpu_s=gpu_s, ms_per_step=1e3 * wall / steps,
@@ -287,15 +352,15 @@ def main():
         note(f"fp32 leg: {leg['ms_per_step']:.1f} ms per step")
         line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
-    if args.two_d:
-        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, args.fp64_check)
+    if not args.no_two_d:
+        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, not args.no_fp64_check_2d, args.two_d_graph)
     if args.sweep:
         line["uneven_sweep"] = uneven_sweep(args.sweep_steps, args.sweep_streams, args.fp64_check)
     if args.paper:
         line["paper_workload"] = paper_workload(args.paper_steps)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(inputs.model_dict(base, zeta=1.0))
-        line["cpu_baseline"] = cb
+        line["cpu_baseline"] = cpu_baseline([inputs.model_dict(base, zeta=z) for z in zetas])
+        note("cpu baseline done")
     print(json.dumps(line, default=float))
 
 
@@ -324,7 +389,8 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
                batch_streams=streams,
                substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
                cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
-               finite=bool(all(np.all(np.isfinite(r)) for r in R)))
+               finite=bool(all(np.all(np.isfinite(r)) for r in R)),
+               growing_member_ids=info["growing"], growth_flag=sweep.GROWTH_FLAG)
     note(f"sweep: FP32 run {t2 - t1:.1f} s")
     if fp64_check:
         from paper_1706_09590_amd import qhfpe
@@ -337,15 +403,19 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
             errs.append(float(np.max(np.abs(i32 - i64)) / np.max(np.abs(i64))))
         errs = np.array(errs)
         note("sweep: FP64 rerun done")
-        # members whose discretized operator has growing modes amplify rounding:
-        # the error statement is split by the norm growth of a random state
-        # between t = 5 and t = 10 (after transient non-normal growth)
-        amp = sweep.amplification(members, 2500, w["dt"], batches=batches)
-        grow = amp > 2.0
+        # members whose truncated hierarchy has growing modes amplify rounding:
+        # the error statement is split by each member's own state-norm growth
+        # over the second half of the run (the flag run_sweep returns)
+        grow = np.zeros(len(members), dtype=bool)
+        grow[info["growing"]] = True
         out["fp32_spectrum_max_rel_err_vs_fp64"] = float(errs.max())
         out["fp32_spectrum_max_rel_err_vs_fp64_bounded_members"] = float(errs[~grow].max()) if (~grow).any() else None
+        out["bounded_members"] = int((~grow).sum())
         out["fp32_spectrum_median_rel_err_vs_fp64"] = float(np.median(errs))
         out["growing_members"] = int(grow.sum())
+        # the same split by the random-state amplification probe, for comparison
+        amp = sweep.amplification(members, 2500, w["dt"], batches=batches)
+        out["amplification_probe_growing_ids"] = [int(i) for i in np.flatnonzero(amp > 2.0)]
         out["growing_members_min_zeta"] = float(min(members[i]["zeta"] for i in np.flatnonzero(grow))) if grow.any() else None
         out["growing_members_min_depth"] = int(min(members[i]["depth"] for i in np.flatnonzero(grow))) if grow.any() else None
     return out
@@ -353,16 +423,24 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
 
 def paper_workload(nsteps: int = 0):
     """The paper's own model (Sec. III): Morse/Gaussian surfaces with a
-    q-dependent coupling, 128 x 512 mesh, depth 5, underdamped bath; linear
-    absorption R1 every step from the relaxed hierarchy W_eq.  FP64 state,
-    then FP32 state with its spectrum error against FP64.  Reports wall time and cell-updates/s of each
+    q-dependent coupling on the 128 x 512 mesh, underdamped (depth 5) and
+    overdamped (zeta = 400 cm^-1, gamma -> infinity: depth 0, Eq. (heomW))."""
+    from paper_1706_09590_amd import inputs
+    out = paper_case(inputs.PAPER_ABSORPTION, nsteps)
+    out["overdamped"] = paper_case(inputs.PAPER_OVERDAMPED, nsteps)
+    return out
+
+
+def paper_case(w: dict, nsteps: int = 0):
+    """Linear absorption R1 every step from the relaxed hierarchy W_eq of one
+    of the paper's cases.  FP64 state, then FP32 state with its spectrum
+    error against FP64.  Reports wall time and cell-updates/s of each
     propagation, dt times the power-iteration spectral radius (RK4 is stable
     below about 2.8) and the absorption maximum in cm^-1."""
     import numpy as np
     import torch
 
     from paper_1706_09590_amd import inputs, qhfpe, sweep
-    w = inputs.PAPER_ABSORPTION
     m = w["model"]
     surf = w["surfaces"]
     nsteps = nsteps or w["nsteps"]
@@ -371,8 +449,8 @@ def paper_workload(nsteps: int = 0):
                                       prepare=lambda P: P.set_potential_morse_gauss(**surf))[0])
     om = torch.linspace(w["omega_range"][0], w["omega_range"][1], w["n_omega"], dtype=torch.float64, device=dev)
     cells = (m["depth"] + 1) * m["nq"] * m["np"]
-    out = dict(mesh=f"{m['np']} x {m['nq']} (p x q)", depth=m["depth"], rk4_steps=nsteps, dt=m["dt"],
-               dt_times_spectral_radius=rho * m["dt"])
+    out = dict(mesh=f"{m['np']} x {m['nq']} (p x q)", depth=m["depth"], zeta=m["zeta"], rk4_steps=nsteps,
+               dt=m["dt"], dt_times_spectral_radius=rho * m["dt"])
     # W_eq: FP64 real-time relaxation of the full hierarchy from the harmonic
     # thermal state (reported apart)
     # at the largest stable RK4 step (the stationary state does not depend on it)
@@ -414,11 +492,17 @@ def paper_workload(nsteps: int = 0):
     return out
 
 
-def two_d_spectrum(scale: int = 1, fp64_check: bool = False):
+def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False):
     """Wall time of the batched 2D correlation spectrum: FP64 equilibration of
-    the 128x128 depth-6 hierarchy (reported apart), then t1 / t2 preparation
-    and all t3 propagations as one batch (FP32 state, FP64 traces), and the
-    correlation and transient-absorption spectra on [0, 20]^2 (step 0.05)."""
+    the 128x128 depth-6 hierarchy (reported apart), then the t1 / t2
+    preparation and all t3 propagations as one batch (FP32 state, FP64
+    traces), and the correlation and transient-absorption spectra on
+    [0, 20]^2 (step 0.05).  The t3 propagation is bracketed by HIP events on
+    the protocol's stream: its average stage launch gives the roofline
+    (algorithmic bytes 3 n_s^2 w per cell and stage).  graph: the whole
+    protocol is recorded into one graph first (record and instantiate
+    reported apart) and launched.  fp64_check: the same spectra from the
+    FP64 state (untimed), for the FP32 error statement."""
     import torch
 
     from paper_1706_09590_amd import inputs, response
@@ -426,6 +510,7 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = False):
     m = w["model"]
     t1s = w["t1_steps"][:: scale]
     t2s = w["t2_steps"][:: scale]
+    n3, s3 = w["n3_steps"], w["stride3"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # relaxation at the largest stable RK4 step (the stationary state does not
@@ -433,29 +518,61 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = False):
     dt_relax = response.relax_step(m)
     W_eq, steps, res = response.equilibrate(m, tol=1e-10, max_steps=100000, check_every=500, dt=dt_relax)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t_eq = time.perf_counter() - t0
     note(f"2D spectrum: equilibrated in {steps} steps")
-    R3 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp32")
     om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
     dt = m["dt"]
-    Ic = response.correlation_spectra(R3, (t1s[1] - t1s[0]) * dt, w["stride3"] * dt, om, om)
-    It = response.transient_absorption(R3, w["stride3"] * dt, om)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+
+    def spectra(R3):
+        Ic = response.correlation_spectra(R3, (t1s[1] - t1s[0]) * dt, s3 * dt, om, om)
+        It = response.transient_absorption(R3, s3 * dt, om, t1s)
+        return Ic, It
+
+    pr = response.ThirdOrderProtocol(m, W_eq, t1s, t2s, n3, s3, precision="fp32")
+    out = {}
+    try:
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        if graph:
+            torch.cuda.synchronize()
+            g0 = time.perf_counter()
+            g = pr.record()
+            out["graph"] = dict(record_and_instantiate_s=time.perf_counter() - g0, nodes=g.nodes)
+            note(f"2D spectrum: graph of {g.nodes} nodes recorded")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pr.run(None if graph else ev)
+        R3 = pr.result()
+        Ic, It = spectra(R3)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        pr.close()
     cells = (m["depth"] + 1) * m["nq"] * m["np"]
-    prep = sum(t1s[-1:]) + len(t1s) * t2s[-1]
-    updates = cells * (len(t1s) * len(t2s) * w["n3_steps"] + prep)
-    out = dict(wall_s=t2 - t1, equilibration_s=t1 - t0, equilibration_steps=steps, equilibration_residual=res,
-               n_t1=len(t1s), n_t2=len(t2s), n3_steps=w["n3_steps"], cell_updates=updates,
-               cell_updates_per_s=updates / (t2 - t1), finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
+    prep = t1s[-1] + len(t1s) * t2s[-1]
+    B = len(t1s) * len(t2s)
+    updates = cells * (B * n3 + prep)
+    out.update(wall_s=t2 - t1, equilibration_s=t_eq, equilibration_steps=steps, equilibration_residual=res,
+               n_t1=len(t1s), n_t2=len(t2s), n3_steps=n3, members=B, cell_updates=updates,
+               cell_updates_per_s=updates / (t2 - t1), mode="graph" if graph else "eager",
+               finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
+    if not graph:
+        t3_s = ev[0].elapsed_time(ev[1]) / 1e3
+        launch_s = t3_s / (4 * n3)
+        nc = m["n_states"] ** 2
+        bpl = 3 * nc * 4 * cells * B  # FP32 state: 3 n_s^2 w per cell and stage
+        bpl_f = 2.5 * nc * 4 * cells * B
+        out["t3_roofline"] = dict(bound="hbm", achieved=round(bpl / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                                  unit="GB/s", frac=round(bpl / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                                  avg_stage_launch_us=round(launch_s * 1e6, 2), bytes_per_stage_launch=bpl,
+                                  frac_factored_bytes=round(bpl_f / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                                  t3_propagation_s=t3_s)
     note(f"2D spectrum: FP32 run {t2 - t1:.1f} s")
     if fp64_check:
-        # the same spectra from the FP64 state (untimed): the FP32 error statement
-        R64 = response.third_order_response(m, W_eq, t1s, t2s, w["n3_steps"], w["stride3"], precision="fp64")
-        Ic64 = response.correlation_spectra(R64, (t1s[1] - t1s[0]) * dt, w["stride3"] * dt, om, om)
-        It64 = response.transient_absorption(R64, w["stride3"] * dt, om)
+        R64 = response.third_order_response(m, W_eq, t1s, t2s, n3, s3, precision="fp64")
+        Ic64, It64 = spectra(R64)
         out["fp32_corr_max_rel_err_vs_fp64"] = float((Ic - Ic64).abs().max() / Ic64.abs().max())
         out["fp32_tas_max_rel_err_vs_fp64"] = float((It - It64).abs().max() / It64.abs().max())
+        note("2D spectrum: FP64 rerun done")
     return out
 
 

@@ -23,10 +23,12 @@
  *  - Work is enqueued on the handle's stream (qhfpe_step's member groups
  *    run on their own streams between an event fork and join on it).
  *    qhfpe_create, qhfpe_set_state, qhfpe_set_member_bath,
- *    qhfpe_set_potential, qhfpe_autotune, qhfpe_step, qhfpe_residual and
- *    qhfpe_relax synchronise that stream before they return (they upload
- *    tables or read a result or a status flag back); the other calls are
- *    asynchronous.
+ *    qhfpe_set_potential, qhfpe_autotune, qhfpe_step, qhfpe_status,
+ *    qhfpe_residual and qhfpe_relax synchronise that stream before they
+ *    return (they upload tables or read a result or a status flag back);
+ *    the other calls are asynchronous.  Only asynchronous calls may be
+ *    recorded into a graph (qhfpe_graph_begin); they enqueue kernels and
+ *    event waits only (no memset or memcpy nodes).
  *  - A handle is used by one host thread at a time; different handles may
  *    be used from different threads.
  *  - Canonical state layout ("canon"): interleaved complex128 (re, im)
@@ -76,7 +78,10 @@ typedef struct qhfpe_params {
   double q_min, q_max, p_min, p_max;
   double mass, hbar;
   double zeta, gamma, beta;    /* Drude bath: J(w) = (m zeta/pi) w gamma^2/(gamma^2 + w^2) */
-  double dt;                   /* RK4 step */
+  double dt;                   /* RK4 step.  Substeps are the caller's choice of dt and of
+                                  qhfpe_step's sampling stride: s substeps per output interval T
+                                  are dt = T / s with stride s (the response is still sampled
+                                  every T). */
   /* U_jl(x) = sum_k poly[j][l][k] x^k.  Diagonal entries: any quartic.
    * Off-diagonal entries: constants (applied pointwise); a q-dependent
    * coupling (k >= 1 non-zero) needs two states and np = 128 or 256 (the
@@ -109,8 +114,10 @@ int qhfpe_destroy(qhfpe_t* h);
  * 1e-12 max |H|.  Synchronous. */
 int qhfpe_set_state(qhfpe_t* h, const double* d_canon, int32_t phase, int32_t member);
 
-/* Write the canonical state (member -1: all, into [B][...]; else one
- * member into [1][...]), including the phase factor i^phase. */
+/* Write the canonical state: the hierarchy elements W^(n)_jk(p, q) of
+ * Sec. II, Eq. (heom), n = 0..N, as full complex matrices in (j, k),
+ * including the phase factor i^phase of the impulsive excitations (member
+ * -1: all, into [B][...]; else one member into [1][...]). */
 int qhfpe_get_state(qhfpe_t* h, double* d_canon, int32_t member);
 int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
 
@@ -207,10 +214,26 @@ int qhfpe_apply_dipole(qhfpe_t* h, int32_t mode);
  * If d_resp != NULL it receives, per member, the complex FP64 trace
  * Tr{mu W^(0)} (including i^phase) at t = 0 and after every stride steps:
  * d_resp[B][nsteps/stride + 1][2]; nsteps must be a multiple of stride.
- * Synchronous; returns QHFPE_ENONFINITE if a sample is not finite. */
+ * Synchronous; returns QHFPE_ENONFINITE if a sample (or, without d_resp,
+ * the final trace) is not finite.  QHFPE_ESTATE while the stream records a
+ * graph (use qhfpe_step_async). */
 int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp);
 
-/* Current Tr{mu W^(0)} per member, d_out[B][2] (FP64, including i^phase). */
+/* The same propagation, enqueued only: no status is read back, so the call
+ * returns before the GPU work ends and can be recorded into a graph.  A
+ * non-finite sample sets the handle's status flag, which stays set until
+ * qhfpe_status (or qhfpe_step, which clears it first) reads it. */
+int qhfpe_step_async(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp);
+
+/* Wait for the handle's stream and report the status flag of the
+ * propagations enqueued since the last check: QHFPE_ENONFINITE if a trace
+ * sample was not finite (the flag is then cleared), else QHFPE_OK.
+ * Synchronous (QHFPE_ESTATE while the stream records a graph). */
+int qhfpe_status(qhfpe_t* h);
+
+/* Current Tr{mu W^(0)} per member, d_out[B][2] (FP64, including i^phase):
+ * the trace of Sec. III, Eqs. (R1) and (R3) at the present time of each
+ * member, without the (i/hbar)^k factor. */
 int qhfpe_response(qhfpe_t* h, double* d_out);
 
 /* Test hook: state <- L(state), the right-hand side of Eq. (heom)/(GMFP),
@@ -229,14 +252,43 @@ int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every,
                 int64_t* h_steps_done, double* h_residual);
 
 /* Copy count members src[src_member..] -> dst[dst_member..] device to
- * device (multi-time protocol of Sec. III).  Both handles must share
- * n_states, nq, np, depth and precision; dst takes src's phase.  Within
- * one handle the two ranges must not overlap (QHFPE_EINVAL).  The copy is
- * enqueued on dst's stream; when the handles' streams differ the call
- * waits for src's stream before the copy and for the copy before it
- * returns, so neither handle's later work can race with it. */
+ * device (multi-time protocol of Sec. III: the states after G(t1) and
+ * G(t2) seed the next propagations).  Both handles must share n_states,
+ * nq, np, depth and precision; dst takes src's phase.  The phase is one per
+ * handle, so a copy with another phase than dst's must cover all of dst's
+ * members unless dst holds no state yet (created and never loaded by
+ * qhfpe_set_state, qhfpe_init_thermal or a copy): QHFPE_ESTATE otherwise.
+ * Within one handle the two ranges must not overlap (QHFPE_EINVAL).  The
+ * copy is a kernel on dst's stream; when the handles' streams differ it
+ * waits for src's pending work and src's later work waits for it (events
+ * only: the call stays asynchronous and can be recorded into a graph). */
 int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst,
                        int32_t dst_member, int32_t count);
+
+/* Device-to-device copy of bytes (d_dst, d_src 16-byte aligned, ranges
+ * not overlapping) by the library's streaming kernel: 16-byte loads and
+ * stores per lane, every lane's loads issued before its stores.  It is the
+ * copy qhfpe_copy_members uses, and the plain copy of known size that
+ * bandwidth measurements compare against.  Asynchronous on stream. */
+int qhfpe_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
+
+/* Graphs of the asynchronous calls (the multi-time protocol of Sec. III as
+ * one launch).  qhfpe_graph_begin starts recording what this thread
+ * enqueues on stream (hipStreamBeginCapture, thread-local mode; stream must
+ * not be NULL); library calls on handles of that stream are then recorded,
+ * not run.  Synchronous calls fail while recording.  Host-side bookkeeping
+ * (each handle's phase) advances at recording time, so a graph replays the
+ * recorded sequence: a graph that should give the same result on every
+ * launch starts by loading its initial state (e.g. qhfpe_copy_members from
+ * a handle that holds it).  qhfpe_graph_end ends the recording and
+ * instantiates the graph; qhfpe_graph_launch runs it on a stream;
+ * qhfpe_graph_nodes reports its node count. */
+typedef struct qhfpe_graph qhfpe_graph_t;
+int qhfpe_graph_begin(void* stream);
+int qhfpe_graph_end(void* stream, qhfpe_graph_t** out);
+int qhfpe_graph_nodes(const qhfpe_graph_t* g, size_t* nodes);
+int qhfpe_graph_launch(qhfpe_graph_t* g, void* stream);
+int qhfpe_graph_destroy(qhfpe_graph_t* g);
 
 /* Sec. III, Eq. (I1) (and Eq. (transient-absorption) for an R3(t, T, 0)
  * series): d_out[w] = omega_w Im sum_s c_s dt exp(i omega_w s dt) R[s],

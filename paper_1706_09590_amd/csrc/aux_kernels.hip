@@ -297,6 +297,36 @@ __global__ void spectrum_corr_t1_kernel(const double* __restrict__ work, int n1,
   out[(long long)w * nw1 + a] = acc * dt1;
 }
 
+__global__ void clear_flag_kernel(int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
+// Streaming device copy: every lane moves kCopyUnroll 16-byte vectors, all
+// loads issued before the first store, consecutive lanes on consecutive
+// vectors (each load and store instruction of a wave covers 1 KiB).
+constexpr int kCopyUnroll = 4;
+__global__ void __launch_bounds__(kBlock)
+    stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n16) {
+  const long long base = (long long)blockIdx.x * (kBlock * kCopyUnroll) + threadIdx.x;
+  uint4 v[kCopyUnroll];
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const long long i = base + (long long)k * kBlock;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const long long i = base + (long long)k * kBlock;
+    if (i < n16) dst[i] = v[k];
+  }
+}
+
+// the bytes past the last whole 16-byte vector (fewer than 16)
+__global__ void copy_tail_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 inline dim3 cell_grid(const GridDesc& g, int nmembers) {
   const long long cells = (long long)g.levels * g.nq * g.np;
   return dim3((unsigned)((cells + kBlock - 1) / kBlock), (unsigned)nmembers);
@@ -389,6 +419,33 @@ hipError_t launch_norm_partials(const GridDesc& g, const void* packed, double* r
   QHFPE_DISPATCH(g, F);
 #undef F
   return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) return hipErrorInvalidValue;
+  const long long n16 = (long long)(bytes / 16);
+  const int tail = (int)(bytes % 16);
+  if (n16 > 0) {
+    const long long per_block = (long long)kBlock * kCopyUnroll;
+    const long long blocks = (n16 + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (tail) {
+    hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, static_cast<const unsigned char*>(src) + 16 * n16,
+                       static_cast<unsigned char*>(dst) + 16 * n16, tail);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_spectrum_abs(const double* series, long long n, double dt, const double* omega, int n_omega,

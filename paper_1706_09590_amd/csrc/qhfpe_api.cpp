@@ -306,6 +306,11 @@ struct qhfpe_handle {
   hipStream_t gstream[kMaxGroups] = {};
   hipEvent_t gfork = nullptr;
   hipEvent_t gjoin[kMaxGroups] = {};
+  // orders qhfpe_copy_members between the streams of two handles
+  hipEvent_t xevent = nullptr;
+  // false until a state is loaded (set_state, init_thermal, copy_members):
+  // a partial copy may then set the phase of the (all-zero) state
+  bool loaded = false;
 
   ~qhfpe_handle() {
     for (int g = 0; g < groups_made; ++g) {
@@ -313,6 +318,7 @@ struct qhfpe_handle {
       if (gjoin[g]) hipEventDestroy(gjoin[g]);
     }
     if (gfork) hipEventDestroy(gfork);
+    if (xevent) hipEventDestroy(xevent);
   }
 
   // Default for small batches, where one launch per stage leaves most SIMDs
@@ -452,6 +458,12 @@ struct qhfpe_handle {
   }
 };
 
+struct qhfpe_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t nodes = 0;
+};
+
 namespace {
 
 int check_handle(const qhfpe_t* h) {
@@ -484,6 +496,13 @@ int read_flag(qhfpe_t* h, int* value) {
   HIP_TRY(hipMemcpyAsync(value, h->flag(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return QHFPE_OK;
+}
+
+// true while the handle's stream records into a graph
+bool capturing(const qhfpe_t* h) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(h->stream, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusActive;
 }
 
 // ||buf||_2 per member into out[b] (host)
@@ -598,7 +617,8 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bath(), bath.data(), bath.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->y(), 0, 3 * L.state_bytes, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->flag(), 0, sizeof(int), h->stream);
+  if (e == hipSuccess) e = launch_clear_flag(h->flag(), h->stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->xevent, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     delete h;
@@ -724,6 +744,8 @@ int qhfpe_set_streams(qhfpe_t* h, int32_t groups) {
   if (int rc = check_handle(h)) return rc;
   if (groups < 0 || groups > kMaxGroups) return fail(QHFPE_EINVAL, "groups must be in [0, %d]", kMaxGroups);
   h->groups_req = groups;
+  // the streams of the groups exist before any step (and so before a capture)
+  if (h->groups() > 1) HIP_TRY(h->make_groups(h->groups()));
   return QHFPE_OK;
 }
 
@@ -770,6 +792,7 @@ int qhfpe_set_state(qhfpe_t* h, const double* d_canon, int32_t phase, int32_t me
                          count * mb, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->phase = phase;
+  h->loaded = true;
   return QHFPE_OK;
 }
 
@@ -789,6 +812,7 @@ int qhfpe_init_thermal(qhfpe_t* h, double omega, const double* d_noise) {
   HIP_TRY(launch_thermal(h->grid(), h->y(), h->p.q_min, h->dq, h->p.p_min, h->dp, h->bath(), omega, h->p.mass,
                          h->p.hbar, d_noise, h->stream));
   h->phase = 0;
+  h->loaded = true;
   return QHFPE_OK;
 }
 
@@ -800,14 +824,23 @@ int qhfpe_apply_dipole(qhfpe_t* h, int32_t mode) {
   return QHFPE_OK;
 }
 
-int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
+}  // extern "C"
+
+namespace {
+
+int check_step_args(const qhfpe_t* h, int64_t nsteps, int32_t stride, const double* d_resp) {
   if (int rc = check_handle(h)) return rc;
   if (nsteps < 0) return fail(QHFPE_EINVAL, "nsteps must be >= 0");
   if (stride < 1) return fail(QHFPE_EINVAL, "stride must be >= 1");
   if (d_resp && nsteps % stride) return fail(QHFPE_EINVAL, "nsteps must be a multiple of stride");
+  return QHFPE_OK;
+}
+
+// Enqueue nsteps RK4 steps with their trace samples on the handle's stream.
+// Non-finite samples set the handle's flag; nothing is read back.
+int step_enqueue(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
   const double dt = h->p.dt;
   const long long nsamples = d_resp ? nsteps / stride + 1 : 0;
-  HIP_TRY(hipMemsetAsync(h->flag(), 0, sizeof(int), h->stream));
   int slot = 0;
   long long base = 0;
   if (d_resp) {
@@ -830,7 +863,10 @@ int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
   StageArgs s4 = h->stage_args(h->va(), h->vb(), h->y(), kA2 * dt);
   // member groups: group g holds members first[g] .. first[g + 1] - 1 and
   // runs on its own stream between a fork and a join on the handle's stream
-  const int G = nsteps > 0 ? h->groups() : 1;
+  int G = nsteps > 0 ? h->groups() : 1;
+  // no stream is created while the handle's stream records a graph; the
+  // results do not depend on the grouping
+  if (G > h->groups_made && capturing(h)) G = 1;
   int first[kMaxGroups + 1];
   for (int g = 0; g <= G; ++g) first[g] = (int)((long long)g * h->p.batch / G);
   hipStream_t gs[kMaxGroups];
@@ -893,11 +929,54 @@ int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
     if (int rc = trace_into(h, 0)) return rc;
     if (int rc = finalize(h, 1, nullptr, 0, 0)) return rc;
   }
-  int flag = 0;
-  if (int rc = read_flag(h, &flag)) return rc;
-  if (flag) return fail(QHFPE_ENONFINITE, "non-finite trace during propagation (dt too large?)");
   return QHFPE_OK;
 }
+
+// Read and clear the handle's non-finite flag (synchronises its stream).
+int take_flag(qhfpe_t* h) {
+  int flag = 0;
+  if (int rc = read_flag(h, &flag)) return rc;
+  if (flag) {
+    HIP_TRY(launch_clear_flag(h->flag(), h->stream));
+    return fail(QHFPE_ENONFINITE, "non-finite trace during propagation (dt too large?)");
+  }
+  return QHFPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qhfpe_step(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
+  if (int rc = check_step_args(h, nsteps, stride, d_resp)) return rc;
+  if (capturing(h)) return fail(QHFPE_ESTATE, "qhfpe_step synchronises: use qhfpe_step_async while capturing");
+  HIP_TRY(launch_clear_flag(h->flag(), h->stream));
+  if (int rc = step_enqueue(h, nsteps, stride, d_resp)) return rc;
+  return take_flag(h);
+}
+
+int qhfpe_step_async(qhfpe_t* h, int64_t nsteps, int32_t stride, double* d_resp) {
+  if (int rc = check_step_args(h, nsteps, stride, d_resp)) return rc;
+  return step_enqueue(h, nsteps, stride, d_resp);
+}
+
+int qhfpe_status(qhfpe_t* h) {
+  if (int rc = check_handle(h)) return rc;
+  if (capturing(h)) return fail(QHFPE_ESTATE, "qhfpe_status synchronises: not allowed while capturing");
+  return take_flag(h);
+}
+
+int qhfpe_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* stream) {
+  if (bytes == 0) return QHFPE_OK;
+  if (!d_dst || !d_src) return fail(QHFPE_EINVAL, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(d_dst) | reinterpret_cast<uintptr_t>(d_src)) % 16)
+    return fail(QHFPE_EINVAL, "pointers must be 16-byte aligned");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(d_dst), b = reinterpret_cast<uintptr_t>(d_src);
+  if (a < b + bytes && b < a + bytes && a != b) return fail(QHFPE_EINVAL, "overlapping ranges");
+  HIP_TRY(launch_stream_copy(d_dst, d_src, bytes, static_cast<hipStream_t>(stream)));
+  return QHFPE_OK;
+}
+
 
 int qhfpe_response(qhfpe_t* h, double* d_out) {
   if (int rc = check_handle(h)) return rc;
@@ -966,16 +1045,81 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int
   if (src == dst && src_member < dst_member + count && dst_member < src_member + count && src_member != dst_member)
     return fail(QHFPE_EINVAL, "overlapping member ranges within one handle");
   if (count == 0 || (src == dst && src_member == dst_member)) return QHFPE_OK;
+  // the phase i^k is one per handle: a partial copy into a loaded handle of
+  // another phase would leave its other members read with the wrong phase
+  const bool whole = dst_member == 0 && count == dst->p.batch;
+  if (dst->loaded && src->phase != dst->phase && !whole)
+    return fail(QHFPE_ESTATE, "copying %d of %d members with phase %d into a handle of phase %d", count,
+                dst->p.batch, src->phase, dst->phase);
   const size_t mb = (size_t)src->L.member_elems * src->L.elem;
-  // on different streams: src's pending steps finish before the copy reads
-  // its state, and the copy finishes before src's later work can change it
+  // on different streams: the copy waits for src's pending work, and src's
+  // later work waits for the copy (events only, so the call can be captured)
   const bool two = src->stream != dst->stream;
-  if (two) HIP_TRY(hipStreamSynchronize(src->stream));
-  HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst->y()) + dst_member * mb,
-                         static_cast<const char*>(src->y()) + src_member * mb, count * mb,
-                         hipMemcpyDeviceToDevice, dst->stream));
-  if (two) HIP_TRY(hipStreamSynchronize(dst->stream));
+  if (two) {
+    HIP_TRY(hipEventRecord(src->xevent, src->stream));
+    HIP_TRY(hipStreamWaitEvent(dst->stream, src->xevent, 0));
+  }
+  HIP_TRY(launch_stream_copy(static_cast<char*>(dst->y()) + dst_member * mb,
+                             static_cast<const char*>(src->y()) + src_member * mb, count * mb, dst->stream));
+  if (two) {
+    HIP_TRY(hipEventRecord(dst->xevent, dst->stream));
+    HIP_TRY(hipStreamWaitEvent(src->stream, dst->xevent, 0));
+  }
   dst->phase = src->phase;
+  dst->loaded = true;
+  return QHFPE_OK;
+}
+
+int qhfpe_graph_begin(void* stream) {
+  if (!stream) return fail(QHFPE_EINVAL, "graph capture needs a stream of its own (not the NULL stream)");
+  HIP_TRY(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+  return QHFPE_OK;
+}
+
+int qhfpe_graph_end(void* stream, qhfpe_graph_t** out) {
+  if (!out) return fail(QHFPE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!stream) return fail(QHFPE_EINVAL, "stream is NULL");
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(static_cast<hipStream_t>(stream), &g));
+  hipGraphExec_t x = nullptr;
+  hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(QHFPE_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  size_t nodes = 0;
+  hipGraphGetNodes(g, nullptr, &nodes);
+  qhfpe_graph_t* r = new (std::nothrow) qhfpe_graph();
+  if (!r) {
+    hipGraphExecDestroy(x);
+    hipGraphDestroy(g);
+    return fail(QHFPE_EINVAL, "out of host memory");
+  }
+  r->graph = g;
+  r->exec = x;
+  r->nodes = nodes;
+  *out = r;
+  return QHFPE_OK;
+}
+
+int qhfpe_graph_nodes(const qhfpe_graph_t* g, size_t* nodes) {
+  if (!g || !nodes) return fail(QHFPE_EINVAL, "NULL pointer");
+  *nodes = g->nodes;
+  return QHFPE_OK;
+}
+
+int qhfpe_graph_launch(qhfpe_graph_t* g, void* stream) {
+  if (!g) return fail(QHFPE_EINVAL, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return QHFPE_OK;
+}
+
+int qhfpe_graph_destroy(qhfpe_graph_t* g) {
+  if (!g) return QHFPE_OK;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  delete g;
   return QHFPE_OK;
 }
 

@@ -123,6 +123,10 @@ hipError_t launch_trace_partials(const GridDesc& g, const void* packed, const do
 hipError_t launch_finalize(int batch, int ntiles, int nslots, const double* partials,
                            double scale, int phase, double* resp, long long resp_stride,
                            long long resp_offset, int* flag, hipStream_t s);
+hipError_t launch_clear_flag(int* flag, hipStream_t s);
+// device-to-device copy of `bytes` (dst and src 16-byte aligned) by a
+// streaming kernel: no memcpy or memset node when captured into a graph
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_norm_partials(const GridDesc& g, const void* packed, double* red,
                                 int* nblocks_per_member, hipStream_t s);
 hipError_t launch_spectrum_abs(const double* series, long long n, double dt, const double* omega,

@@ -112,6 +112,18 @@ PAPER_ABSORPTION = dict(
     relax_tol=1e-7, relax_max_steps=300000, omega_range=(150.0, 250.0), n_omega=2001)
 
 
+# The paper's overdamped case (Sec. III): the same surfaces and mesh with
+# zeta = 400 cm^-1 (4 omega_0) and gamma -> infinity, i.e. depth N = 0 and
+# the high-temperature constants (c0 = m zeta / beta, c_delta = 0): Eq. (GMFP)
+# at N = 0 is then Eq. (heomW), where gamma does not enter (the damping term
+# is -n gamma W^(n) = 0 at n = 0), so any finite gamma gives the same
+# operator; the value below only satisfies the parameter check.
+PAPER_OVERDAMPED = dict(
+    model=dict(PAPER_ABSORPTION["model"], depth=0, zeta=4.0, gamma=5.0, low_temp_correction=False),
+    surfaces=PAPER_ABSORPTION["surfaces"], nsteps=20000, stride=1, thermal_omega=1.0,
+    relax_tol=1e-7, relax_max_steps=300000, omega_range=(150.0, 250.0), n_omega=2001)
+
+
 # Uneven batched sweep: 256 members on grids 96^2..256^2, depths 4..10, a
 # quarter of them three-state, random Drude baths; 5000 RK4 steps of 0.002
 # (sampled every step; members that need it take RK4 substeps).

@@ -87,6 +87,14 @@ def lib():
         "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
         "qhfpe_apply_dipole": ([_vp, _c_i32], _c_int),
         "qhfpe_step": ([_vp, _c_i64, _c_i32, _vp], _c_int),
+        "qhfpe_step_async": ([_vp, _c_i64, _c_i32, _vp], _c_int),
+        "qhfpe_status": ([_vp], _c_int),
+        "qhfpe_stream_copy": ([_vp, _vp, ctypes.c_size_t, _vp], _c_int),
+        "qhfpe_graph_begin": ([_vp], _c_int),
+        "qhfpe_graph_end": ([_vp, ctypes.POINTER(_vp)], _c_int),
+        "qhfpe_graph_nodes": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _c_int),
+        "qhfpe_graph_launch": ([_vp, _vp], _c_int),
+        "qhfpe_graph_destroy": ([_vp], _c_int),
         "qhfpe_response": ([_vp, _vp], _c_int),
         "qhfpe_apply_rhs": ([_vp], _c_int),
         "qhfpe_residual": ([_vp, ctypes.POINTER(_c_dbl)], _c_int),
@@ -274,10 +282,14 @@ class Propagator:
     def apply_dipole(self):
         _check(lib().qhfpe_apply_dipole(self.handle, COMMUTATOR))
 
-    def step(self, nsteps: int, stride: int = 1, record: bool = True, out=None):
+    def step(self, nsteps: int, stride: int = 1, record: bool = True, out=None, asynchronous: bool = False):
+        """nsteps RK4 steps; with record, the trace every stride steps into
+        out (complex128 [B][nsteps/stride + 1], allocated if None).
+        asynchronous: qhfpe_step_async (no status read back; see status())."""
         t = self.torch
+        fn = lib().qhfpe_step_async if asynchronous else lib().qhfpe_step
         if not record:
-            _check(lib().qhfpe_step(self.handle, int(nsteps), int(stride), None))
+            _check(fn(self.handle, int(nsteps), int(stride), None))
             return None
         n = nsteps // stride + 1
         if out is None:
@@ -287,8 +299,13 @@ class Propagator:
             raise ValueError(f"out must be a contiguous complex128 tensor of shape ({self.batch}, {n}) "
                              f"on {self.workspace.device}")
         self._after_torch()
-        _check(lib().qhfpe_step(self.handle, int(nsteps), int(stride), _ptr(out)))
+        _check(fn(self.handle, int(nsteps), int(stride), _ptr(out)))
         return out
+
+    def status(self):
+        """Raise QHFPEError(ENONFINITE) if an asynchronous step saw a
+        non-finite trace since the last check (synchronises the stream)."""
+        _check(lib().qhfpe_status(self.handle))
 
     def response(self):
         t = self.torch
@@ -318,6 +335,61 @@ class Propagator:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+def stream_copy(dst, src, stream=None):
+    """dst <- src (same byte count, 16-byte aligned device tensors) with the
+    library's streaming copy kernel."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(lib().qhfpe_stream_copy(_ptr(dst), _ptr(src), nbytes, ctypes.c_void_p(s.cuda_stream)))
+
+
+class Graph:
+    """A recorded sequence of asynchronous library calls on one stream
+    (qhfpe_graph_begin ... qhfpe_graph_end), replayed by launch()."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.handle = None
+
+    def __enter__(self):
+        _check(lib().qhfpe_graph_begin(ctypes.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        rc = lib().qhfpe_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(rc)
+            self.handle = h
+        elif rc == OK:
+            lib().qhfpe_graph_destroy(h)
+        return False
+
+    @property
+    def nodes(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check(lib().qhfpe_graph_nodes(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else self.stream
+        _check(lib().qhfpe_graph_launch(self.handle, ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().qhfpe_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def spectrum_abs(series, dt: float, omegas, stream=None):

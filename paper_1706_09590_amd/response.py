@@ -73,38 +73,114 @@ def linear_response(model: dict, nsteps: int, stride: int = 1, precision: str = 
     return (1j / model.get("hbar", 1.0)) * tr
 
 
+class ThirdOrderProtocol:
+    """The multi-time protocol of Sec. III for R3 as a sequence of
+    asynchronous library calls on one stream, run once eagerly or recorded
+    into a graph:
+
+      A <- W_eq (copied from a handle that holds it), mu^x;
+      for each t1: G on A up to t1, A -> member i1 of B1;  mu^x on B1;
+      for each t2: G on B1 up to t2, B1 -> members of C;   mu^x on C;
+      G(t3) on all members of C with the trace every stride3 steps.
+
+    Every handle and the output buffer exist before enqueue(), so a recorded
+    graph allocates nothing and can be launched again: it reloads W_eq into A
+    first, so every launch gives the same R3."""
+
+    def __init__(self, model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, stride3: int = 1,
+                 precision: str = "fp32", device=None, stream=None):
+        import torch
+        self.t1_steps, self.t2_steps = list(t1_steps), list(t2_steps)
+        self.n3_steps, self.stride3 = int(n3_steps), int(stride3)
+        self.model = model
+        dev = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        n1, n2 = len(self.t1_steps), len(self.t2_steps)
+        mk = lambda b: qhfpe.Propagator(model, batch=b, precision=precision, device=dev, stream=self.stream)  # noqa: E731
+        self.E, self.A, self.B1, self.C = mk(1), mk(1), mk(n1), mk(n1 * n2)
+        W_eq = torch.as_tensor(W_eq, dtype=torch.complex128)
+        with torch.cuda.stream(self.stream):
+            self.E.set_state(W_eq.to(dev), phase=0)
+        self.trace = torch.empty((n1 * n2, self.n3_steps // self.stride3 + 1), dtype=torch.complex128, device=dev)
+        self.graph = None
+
+    def enqueue(self, t3_events=None):
+        """t3_events: optional pair of timing events (torch.cuda.Event), recorded
+        on the protocol's stream around the t3 propagation (eager runs only)."""
+        import torch
+        A, B1, C = self.A, self.B1, self.C
+        n1 = len(self.t1_steps)
+        with torch.cuda.stream(self.stream):
+            A.copy_members_from(self.E, 0, 0, 1)
+            A.apply_dipole()
+            done = 0
+            for i, s in enumerate(self.t1_steps):
+                A.step(s - done, 1, record=False, asynchronous=True)
+                done = s
+                B1.copy_members_from(A, 0, i, 1)
+            B1.apply_dipole()
+            done = 0
+            for j, s in enumerate(self.t2_steps):
+                B1.step(s - done, 1, record=False, asynchronous=True)
+                done = s
+                C.copy_members_from(B1, 0, j * n1, n1)
+            C.apply_dipole()
+            if t3_events is not None:
+                t3_events[0].record(self.stream)
+            C.step(self.n3_steps, self.stride3, out=self.trace, asynchronous=True)
+            if t3_events is not None:
+                t3_events[1].record(self.stream)
+
+    def record(self):
+        """Record enqueue() into a graph (nothing runs yet)."""
+        self.graph = qhfpe.Graph(self.stream)
+        with self.graph:
+            self.enqueue()
+        return self.graph
+
+    def run(self, t3_events=None):
+        """One pass: the recorded graph if there is one, else eagerly."""
+        if self.graph is not None:
+            self.graph.launch()
+        else:
+            self.enqueue(t3_events)
+
+    def check(self):
+        """Wait for the pass and raise if a trace sample was not finite."""
+        for P in (self.A, self.B1, self.C):
+            P.status()
+
+    def result(self):
+        """R3 = (i/hbar)^3 Tr{...}: complex128 [len(t2)][len(t1)][n3/stride3 + 1]."""
+        self.check()
+        hb = self.model.get("hbar", 1.0)
+        return ((1j / hb) ** 3 * self.trace).reshape(len(self.t2_steps), len(self.t1_steps), -1)
+
+    def close(self):
+        if self.graph is not None:
+            self.graph.close()
+            self.graph = None
+        for P in (self.E, self.A, self.B1, self.C):
+            P.close()
+
+
 def third_order_response(model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, stride3: int = 1,
-                         precision: str = "fp32", device=None):
+                         precision: str = "fp32", device=None, graph: bool = False):
     """R3(t3, t2, t1) = (i/hbar)^3 Tr{mu G(t3) mu^x G(t2) mu^x G(t1) mu^x W_eq}.
 
     t1_steps, t2_steps: increasing step counts of the coherence and waiting
-    times.  W_eq: canonical complex128 [1][...] (phase 0).  Returns complex128
+    times.  W_eq: canonical complex128 [1][...] (phase 0).  graph: record the
+    whole protocol into one graph and launch it (same kernels in the same
+    order, so the same result bit for bit).  Returns complex128
     [len(t2_steps)][len(t1_steps)][n3_steps/stride3 + 1]."""
-    n1, n2 = len(t1_steps), len(t2_steps)
-    W_eq = torch.as_tensor(W_eq, dtype=torch.complex128)
-    A = qhfpe.Propagator(model, batch=1, precision=precision, device=device)
-    A.set_state(W_eq.to(A.device), phase=0)
-    A.apply_dipole()
-    B1 = qhfpe.Propagator(model, batch=n1, precision=precision, device=device)
-    done = 0
-    for i, s in enumerate(t1_steps):
-        A.step(s - done, 1, record=False)
-        done = s
-        B1.copy_members_from(A, 0, i, 1)
-    A.close()
-    B1.apply_dipole()
-    C = qhfpe.Propagator(model, batch=n1 * n2, precision=precision, device=device)
-    done = 0
-    for j, s in enumerate(t2_steps):
-        B1.step(s - done, 1, record=False)
-        done = s
-        C.copy_members_from(B1, 0, j * n1, n1)
-    B1.close()
-    C.apply_dipole()
-    tr = C.step(n3_steps, stride3)
-    C.close()
-    hb = model.get("hbar", 1.0)
-    return ((1j / hb) ** 3 * tr).reshape(n2, n1, -1)
+    pr = ThirdOrderProtocol(model, W_eq, t1_steps, t2_steps, n3_steps, stride3, precision, device)
+    try:
+        if graph:
+            pr.record()
+        pr.run()
+        return pr.result().clone()
+    finally:
+        pr.close()
 
 
 def absorption_spectrum(R1, dt: float, omega):
@@ -117,7 +193,14 @@ def correlation_spectra(R3, dt1: float, dt3: float, omega1, omega3):
     return torch.stack([qhfpe.spectrum_corr(R3[j], dt1, dt3, omega1, omega3) for j in range(R3.shape[0])])
 
 
-def transient_absorption(R3, dt3: float, omega):
+def transient_absorption(R3, dt3: float, omega, t1_steps):
     """I_tas(w, T) = w Im int dt e^{i w t} R3(t, T, 0) for every waiting time T
-    (the t1 = 0 slice, first coherence-time sample): [n2][len(w)]."""
-    return torch.stack([qhfpe.spectrum_abs(R3[j, 0], dt3, omega) for j in range(R3.shape[0])])
+    (the t1 = 0 slice of R3): [n2][len(w)].  t1_steps: the coherence-time
+    steps of R3's second axis; one of them must be 0."""
+    t1_steps = list(t1_steps)
+    if 0 not in t1_steps:
+        raise ValueError("transient absorption needs the coherence time t1 = 0 among t1_steps")
+    i0 = t1_steps.index(0)
+    if len(t1_steps) != R3.shape[1]:
+        raise ValueError(f"R3 has {R3.shape[1]} coherence times, t1_steps {len(t1_steps)}")
+    return torch.stack([qhfpe.spectrum_abs(R3[j, i0], dt3, omega) for j in range(R3.shape[0])])

@@ -13,8 +13,18 @@ library calls release the interpreter lock) was slower.
 RK4 is only stable for dt |lambda| below about 2.8; members with strong,
 hot baths need substeps.  Each member's spectral radius is estimated by
 power iteration with the library's operator (qhfpe_apply_rhs, FP64) and the
-member takes ceil(dt rho / 2.5) substeps of dt / substeps; the response is
-still sampled every dt.
+member takes ceil(dt rho / 2) substeps of dt / substeps; the response is
+still sampled every dt.  Power iteration approaches rho from below, and for
+this real, non-normal operator its ratio oscillates when the dominant
+eigenvalues form a complex pair: the estimate is the largest ratio of the
+last iterations, and the margin 2 (not 2.8) leaves room for what it still
+misses.
+
+Each member also reports the growth of its own state's norm over the second
+half of the run, ||W(T)|| / ||W(T/2)||: deep hierarchies with strong, cold
+baths have growing modes (the truncated hierarchy itself, not the
+discretisation or the precision), and a ratio above 2 flags such a member,
+whose response grows and amplifies rounding.
 
 This module only sequences library calls; all arithmetic runs in the HIP
 library.
@@ -29,7 +39,8 @@ import numpy as np
 
 from . import inputs, qhfpe
 
-RK4_MARGIN = 2.5  # dt * rho allowed per substep (RK4 is stable to about 2.8)
+RK4_MARGIN = 2.0  # dt * rho allowed per substep (RK4 is stable to about 2.8)
+GROWTH_FLAG = 2.0  # ||W(T)|| / ||W(T/2)|| above this marks a growing member
 
 
 def member_model(member: dict, dt: float) -> dict:
@@ -51,8 +62,9 @@ def _shape_key(model: dict):
 def spectral_radius(model: dict, baths, iters: int = 40, seed: int = 7, device=None, renorm_every: int = 8,
                     prepare=None):
     """Power-iteration estimate of the spectral radius of L for each bath
-    (zeta, gamma, beta) on the grid of `model`: ||L^(k+1) W|| / ||L^k W||
-    after `iters` applications, from a seeded random Hermitian hierarchy.
+    (zeta, gamma, beta) on the grid of `model`: the largest ratio
+    ||L^(k+1) W|| / ||L^k W|| over the last `renorm_every` of `iters`
+    applications, from a seeded random Hermitian hierarchy.
     prepare(P), if given, configures the probe handle first (e.g. its
     surfaces).  Returns a float64 array, one value per bath."""
     import torch
@@ -69,7 +81,8 @@ def spectral_radius(model: dict, baths, iters: int = 40, seed: int = 7, device=N
         rho = np.zeros(B)
         for k in range(iters):
             r = P.residual()
-            rho = r[:, 0] / np.maximum(r[:, 1], 1e-300)
+            ratio = r[:, 0] / np.maximum(r[:, 1], 1e-300)
+            rho = np.maximum(rho, ratio) if k >= iters - renorm_every else ratio
             P.apply_rhs()
             if (k + 1) % renorm_every == 0:
                 # rescale every member to unit norm so the iterates stay finite
@@ -108,12 +121,15 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
     """R1(t) for every member, sampled every dt for nsteps steps.
 
     batches: from plan() (computed here if None).  Returns (list of complex128
-    numpy arrays [nsteps+1] in member order, info dict)."""
+    numpy arrays [nsteps+1] in member order, info dict).  info["growth"][i]
+    is ||W(T)|| / ||W(T/2)|| of member i's own state (T = nsteps dt), and
+    info["growing"] the ids of the members whose growth exceeds GROWTH_FLAG."""
     import torch
     qhfpe.lib()  # load the library before the worker threads start
     if batches is None:
         _, batches = plan(members, dt, device=device)
     results = [None] * len(members)
+    growth = np.zeros(len(members))
     dev = torch.device(device if device is not None else "cuda")
     lock = threading.Lock()
     counts = {"cell_updates": 0}
@@ -131,7 +147,13 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 P.autotune(5)  # the fastest stage variant for this batch's shape and size
                 P.init_thermal(thermal_omega)
                 P.apply_dipole()
-                tr = P.step(nsteps * subs, subs)
+                # two halves, with the state's norm at the midpoint and the end
+                half = nsteps // 2
+                tr_a = P.step(half * subs, subs)
+                n_mid = P.residual()[:, 1]
+                tr_b = P.step((nsteps - half) * subs, subs)
+                n_end = P.residual()[:, 1]
+                tr = torch.cat([tr_a, tr_b[:, 1:]], dim=1)
                 R1 = ((1j / mod.get("hbar", 1.0)) * tr).cpu().numpy()
             finally:
                 P.close()
@@ -139,6 +161,7 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
         with lock:
             for j, i in enumerate(ids):
                 results[i] = R1[j]
+                growth[i] = n_end[j] / max(n_mid[j], 1e-300)
             counts["cell_updates"] += cells * len(ids) * nsteps * subs
         return len(ids)
 
@@ -146,7 +169,8 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
     order = sorted(batches, key=lambda b: -(b[0]["depth"] + 1) * b[0]["nq"] * b[0]["np"] * len(b[1]) * b[2])
     with ThreadPoolExecutor(max_workers=max(1, int(streams))) as ex:
         list(ex.map(run_batch, order))
-    info = dict(batches=len(batches), cell_updates=counts["cell_updates"])
+    info = dict(batches=len(batches), cell_updates=counts["cell_updates"], growth=growth,
+                growing=[int(i) for i in np.flatnonzero(growth > GROWTH_FLAG)])
     return results, info
 
 
@@ -188,4 +212,4 @@ def sweep_cell_updates(members, nsteps: int, substeps) -> int:
 
 
 __all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "run_sweep", "amplification",
-           "sweep_cell_updates", "RK4_MARGIN"]
+           "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG"]

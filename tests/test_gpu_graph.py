@@ -1,0 +1,220 @@
+"""Asynchronous stepping, status flags, the streaming copy and recorded
+graphs of the multi-time protocol (Sec. III, Eq. (R3)), through the C-ABI.
+
+A graph replays the same kernels in the same order as the eager run, so its
+R3 must equal the eager R3 bit for bit, on every launch (several launches,
+with unrelated eager work and synchronisation between them)."""
+
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import oracle_model
+from oracle import qhfpe_oracle as O
+from paper_1706_09590_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1706_09590_amd import qhfpe, response  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+SMALL = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], nq=32, np=32, depth=2, dt=0.01)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_equals_eager_bit_for_bit(precision):
+    m = oracle_model(SMALL)
+    W0 = O.thermal_initial_state(m, 1.0)
+    t1s, t2s, n3, s3 = [0, 2, 4, 6], [0, 5], 24, 2
+    say(f"graph vs eager R3, {precision}")
+    eager = response.third_order_response(SMALL, torch.from_numpy(W0[None]), t1s, t2s, n3, s3,
+                                          precision=precision).cpu().numpy()
+    pr = response.ThirdOrderProtocol(SMALL, torch.from_numpy(W0[None]), t1s, t2s, n3, s3, precision=precision)
+    try:
+        pr.trace.zero_()
+        torch.cuda.synchronize()
+        g = pr.record()
+        torch.cuda.synchronize()
+        assert not torch.any(pr.trace != 0)  # nothing ran while recording
+        assert g.nodes > 4 * (t1s[-1] + t2s[-1] + n3)
+        for k in range(3):
+            pr.run()
+            got = pr.result().cpu().numpy()
+            assert np.array_equal(got, eager), k
+            # unrelated eager work and a synchronisation between launches
+            x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+            _ = (x * x).sum().item()
+            pr.trace.zero_()
+            torch.cuda.synchronize()
+    finally:
+        pr.close()
+    ref = O.third_order_response(m, W0, t1s, t2s, n3, s3)
+    assert rel(eager, ref) < (1e-11 if precision == "fp64" else 1e-5)
+
+
+def test_graph_replay_of_a_grouped_two_member_propagation():
+    """A recorded step of a two-member handle with two member groups (fork and
+    join events on the groups' streams) equals the eager step."""
+    d = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], nq=16, np=256, depth=2, dt=0.002)
+    s = torch.cuda.Stream()
+    outs = []
+    for use_graph in (False, True):
+        P = qhfpe.Propagator(d, batch=2, precision="fp64", stream=s)
+        try:
+            P.set_member_bath(1, 1.0, d["gamma"], d["beta"])
+            P.set_streams(2)
+            E = qhfpe.Propagator(d, batch=2, precision="fp64", stream=s)
+            with torch.cuda.stream(s):
+                E.init_thermal(1.0)
+                E.apply_dipole()
+            out = torch.empty((2, 11), dtype=torch.complex128, device="cuda")
+
+            def seq():
+                with torch.cuda.stream(s):
+                    P.copy_members_from(E, 0, 0, 2)
+                    P.step(20, 2, out=out, asynchronous=True)
+
+            if use_graph:
+                g = qhfpe.Graph(s)
+                with g:
+                    seq()
+                g.launch()
+                P.status()
+                first = out.clone()
+                g.launch()
+                P.status()
+                assert torch.equal(first, out)
+                g.close()
+            else:
+                seq()
+                P.status()
+            outs.append(out.cpu().numpy())
+            E.close()
+        finally:
+            P.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_async_step_sets_a_sticky_status_flag():
+    """A step far beyond RK4's stability limit overflows; the asynchronous
+    call returns OK and qhfpe_status reports ENONFINITE once, then clears."""
+    d = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], nq=16, np=16, depth=1, dt=5.0)
+    P = qhfpe.Propagator(d, batch=1, precision="fp64")
+    try:
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        P.step(400, 1, record=True, asynchronous=True)
+        with pytest.raises(qhfpe.QHFPEError) as ei:
+            P.status()
+        assert ei.value.code == qhfpe.ENONFINITE
+        P.status()  # cleared
+        # the synchronous step reports it directly
+        with pytest.raises(qhfpe.QHFPEError) as ei:
+            P.step(10, 1, record=False)
+        assert ei.value.code == qhfpe.ENONFINITE
+    finally:
+        P.close()
+
+
+def test_synchronous_calls_are_refused_while_recording():
+    s = torch.cuda.Stream()
+    P = qhfpe.Propagator(SMALL, batch=1, precision="fp64", stream=s)
+    try:
+        P.init_thermal(1.0)
+        s.synchronize()
+        L = qhfpe.lib()
+        g = qhfpe.Graph(s)
+        with g:
+            assert L.qhfpe_step(P.handle, 2, 1, None) == qhfpe.ESTATE
+            assert L.qhfpe_status(P.handle) == qhfpe.ESTATE
+            with torch.cuda.stream(s):
+                P.step(2, 1, record=False, asynchronous=True)
+        g.launch()
+        P.status()
+        g.close()
+    finally:
+        P.close()
+
+
+def test_copy_members_keeps_one_phase_per_handle():
+    A = qhfpe.Propagator(SMALL, batch=1, precision="fp64")
+    B = qhfpe.Propagator(SMALL, batch=3, precision="fp64")
+    C = qhfpe.Propagator(SMALL, batch=3, precision="fp64")
+    try:
+        A.init_thermal(1.0)
+        A.apply_dipole()                      # phase 1
+        B.copy_members_from(A, 0, 1, 1)       # B never loaded: takes phase 1
+        assert B.phase == 1
+        B.copy_members_from(A, 0, 2, 1)       # same phase
+        A.apply_dipole()                      # phase 2
+        with pytest.raises(qhfpe.QHFPEError) as ei:
+            B.copy_members_from(A, 0, 0, 1)   # partial copy, other phase
+        assert ei.value.code == qhfpe.ESTATE
+        assert B.phase == 1
+        C.init_thermal(1.0)                   # loaded, phase 0
+        C.copy_members_from(B, 0, 0, 3)       # a whole copy may change the phase
+        assert C.phase == 1
+        got = C.get_state().cpu().numpy()
+        ref = B.get_state().cpu().numpy()
+        assert np.array_equal(got, ref)
+    finally:
+        A.close()
+        B.close()
+        C.close()
+
+
+def test_copy_members_between_streams_is_ordered():
+    """Source and destination on different streams: the copy waits for the
+    source's pending steps, and the source's later steps wait for the copy."""
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    A = qhfpe.Propagator(SMALL, batch=1, precision="fp64", stream=s1)
+    B = qhfpe.Propagator(SMALL, batch=1, precision="fp64", stream=s2)
+    R = qhfpe.Propagator(SMALL, batch=1, precision="fp64")
+    try:
+        for P in (A, R):
+            P.init_thermal(1.0)
+            P.apply_dipole()
+        A.step(50, 1, record=False, asynchronous=True)
+        B.copy_members_from(A, 0, 0, 1)
+        A.step(50, 1, record=False, asynchronous=True)
+        R.step(50, 1, record=False)
+        A.status()
+        B.status()
+        assert np.array_equal(B.get_state().cpu().numpy(), R.get_state().cpu().numpy())
+    finally:
+        A.close()
+        B.close()
+        R.close()
+
+
+@pytest.mark.parametrize("nbytes", [16, 1000003, 3 << 24])
+def test_stream_copy_is_exact(nbytes):
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    qhfpe.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+
+
+def test_stream_copy_rejects_bad_arguments():
+    L = qhfpe.lib()
+    x = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.qhfpe_stream_copy(ctypes.c_void_p(x.data_ptr() + 1), ctypes.c_void_p(x.data_ptr() + 512), 64, s) \
+        == qhfpe.EINVAL
+    assert L.qhfpe_stream_copy(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr() + 256), 512, s) \
+        == qhfpe.EINVAL

@@ -95,6 +95,40 @@ def test_paper_model_full_size_rhs_parity():
     assert rhs_case(w["model"], w["surfaces"], "fp64", seed=707) < 1e-12
 
 
+@pytest.mark.parametrize("gamma", [5.0, 1e6])
+def test_paper_overdamped_case_rhs_parity(gamma):
+    """The paper's overdamped case (zeta = 400 cm^-1, gamma -> infinity):
+    depth 0 with the high-temperature constants is Eq. (heomW); gamma does
+    not enter, so two very different gammas give the same operator.  One
+    application on the paper's mesh against the oracle."""
+    w = inputs.PAPER_OVERDAMPED
+    d = inputs.model_dict(w["model"], gamma=gamma)
+    say(f"paper overdamped rhs gamma={gamma}")
+    assert rhs_case(d, w["surfaces"], "fp64", seed=708) < 1e-12
+
+
+def test_paper_overdamped_case_propagation_parity():
+    """Thermal state, mu^x and 20 RK4 steps of the overdamped case on the
+    paper's mesh, traces every 5 steps and the final state, against the
+    oracle."""
+    w = inputs.PAPER_OVERDAMPED
+    d = w["model"]
+    say("paper overdamped propagation")
+    P = qhfpe.Propagator(d, batch=1, precision="fp64")
+    try:
+        P.set_potential_morse_gauss(**w["surfaces"])
+        P.init_thermal(w["thermal_omega"])
+        P.apply_dipole()
+        tr = P.step(20, 5).cpu().numpy()[0]
+        st = P.get_state().cpu().numpy()[0]
+    finally:
+        P.close()
+    m = oracle_of(d, w["surfaces"])
+    W, ref = O.propagate(m, O.dipole_commutator(m, O.thermal_initial_state(m, w["thermal_omega"])), 20, 5)
+    assert rel(tr, ref) < 1e-11
+    assert rel(st, W) < 1e-11
+
+
 def test_q_dependent_coupling_propagation_parity():
     """Thermal state, dipole, 20 RK4 steps with traces every 5, two members
     with different baths in two member groups."""

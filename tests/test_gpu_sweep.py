@@ -124,3 +124,25 @@ def test_amplification_matches_the_oracle():
         ref = np.linalg.norm(W2) / np.linalg.norm(W1)
         assert amp[i] == pytest.approx(ref, rel=1e-9), (i, amp[i], ref)
     assert amp[0] > 5.0 and amp[1] < 1.0
+
+
+def test_member_growth_flag_matches_the_oracle():
+    """run_sweep's per-member growth ||W(T)|| / ||W(T/2)|| of the member's
+    own (dipole-excited thermal) state against the oracle's, and the flag it
+    raises: a strongly damped deep member grows, a weakly damped one does not."""
+    members = [dict(grid=24, depth=6, n_states=2, zeta=4.0, gamma=1.0, beta=2.9),
+               dict(grid=24, depth=2, n_states=2, zeta=0.5, gamma=1.0, beta=1.0)]
+    dt, nsteps = 0.002, 600
+    subs, batches = sweep.plan(members, dt)
+    say(f"growth flag, substeps {list(subs)}")
+    R, info = sweep.run_sweep(members, nsteps, dt, precision="fp64", batches=batches)
+    for i, mem in enumerate(members):
+        m = oracle_model(inputs.model_dict(sweep.member_model(mem, dt), dt=dt / subs[i]))
+        W0 = O.dipole_commutator(m, O.thermal_initial_state(m, 1.0))
+        half = nsteps // 2
+        W1, _ = O.propagate(m, W0, half * int(subs[i]), half, record=False)
+        W2, _ = O.propagate(m, W1, (nsteps - half) * int(subs[i]), nsteps - half, record=False)
+        ref = np.linalg.norm(W2) / np.linalg.norm(W1)
+        assert info["growth"][i] == pytest.approx(ref, rel=1e-9), (i, info["growth"][i], ref)
+    assert info["growing"] == [0]
+    assert info["growth"][1] < 1.0

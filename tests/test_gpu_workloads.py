@@ -168,7 +168,7 @@ def test_third_order_response_and_2d_spectra(precision):
     w1 = np.linspace(0.0, 12.0, 25)
     w3 = np.linspace(0.0, 12.0, 31)
     Ic = response.correlation_spectra(R3, 2 * m.dt, s3 * m.dt, torch.from_numpy(w1), torch.from_numpy(w3))
-    It = response.transient_absorption(R3, s3 * m.dt, torch.from_numpy(w3))
+    It = response.transient_absorption(R3, s3 * m.dt, torch.from_numpy(w3), t1s)
     for j in range(len(t2s)):
         Iref = O.correlation_spectrum(ref[j], 2 * m.dt, s3 * m.dt, w1, w3)
         Tref = O.transient_absorption(ref[j, 0], s3 * m.dt, w3)
