@@ -305,6 +305,19 @@ int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, 
                         const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3,
                         double* d_work, double* d_out, void* stream);
 
+/* qhfpe_spectrum_corr without the d_work argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, hosts
+ * that forbid allocation): the t3 partial sums go to a fixed device array
+ * of the library (1 MiB per GPU, held until the process ends), so the call
+ * allocates nothing.  Limit: n1 * n_w3 <= 65536 (QHFPE_EINVAL above it);
+ * other arguments, results and errors as qhfpe_spectrum_corr.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be ordered by the
+ * caller. */
+int qhfpe_spectrum_corr_noalloc(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3,
+                                const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3,
+                                double* d_out, void* stream);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* qhfpe_last_error(void);
 

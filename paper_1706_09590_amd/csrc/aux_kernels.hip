@@ -2,11 +2,36 @@
 // packed conversion, dipole commutator, thermal initial state, level-0
 // traces, norms and the spectral transforms of Sec. III.
 #include <cmath>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "qhfpe_internal.hpp"
 
 namespace qhfpe {
+
+// Fixed device scratch of the allocation-free entry point (the t3 partial
+// sums of the correlation spectrum): every GPU the library runs on holds its
+// own copy until the process ends.  Host code never uses this name as an
+// address: scratch_pointer() looks the device address up once per device.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_pointer(double** out) {
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
 
 namespace {
 

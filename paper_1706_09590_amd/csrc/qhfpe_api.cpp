@@ -1144,4 +1144,21 @@ int qhfpe_spectrum_corr(const double* d_r3, int32_t n1, int32_t n3, double dt1, 
   return QHFPE_OK;
 }
 
+int qhfpe_spectrum_corr_noalloc(const double* d_r3, int32_t n1, int32_t n3, double dt1, double dt3,
+                                const double* d_w1, int32_t n_w1, const double* d_w3, int32_t n_w3, double* d_out,
+                                void* stream) {
+  if (!d_r3 || !d_w1 || !d_w3 || !d_out) return fail(QHFPE_EINVAL, "NULL pointer");
+  if (n1 < 2 || n3 < 2 || n_w1 < 1 || n_w3 < 1 || !(dt1 > 0) || !(dt3 > 0))
+    return fail(QHFPE_EINVAL, "need n1, n3 >= 2 samples, n_w1, n_w3 >= 1, dt1, dt3 > 0");
+  if (n1 > 65535 || n_w3 > 65535) return fail(QHFPE_EINVAL, "n1 and n_w3 must be <= 65535");
+  if ((size_t)n1 * (size_t)n_w3 * 2 > kScratchDoubles)
+    return fail(QHFPE_EINVAL, "n1 * n_w3 = %lld exceeds the fixed scratch (%zu complex values)",
+                (long long)n1 * n_w3, kScratchDoubles / 2);
+  double* work = nullptr;
+  HIP_TRY(scratch_pointer(&work));
+  HIP_TRY(launch_spectrum_corr(d_r3, n1, n3, dt1, dt3, d_w1, n_w1, d_w3, n_w3, work, d_out,
+                               static_cast<hipStream_t>(stream)));
+  return QHFPE_OK;
+}
+
 }  // extern "C"

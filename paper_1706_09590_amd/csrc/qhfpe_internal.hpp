@@ -131,6 +131,11 @@ hipError_t launch_norm_partials(const GridDesc& g, const void* packed, double* r
                                 int* nblocks_per_member, hipStream_t s);
 hipError_t launch_spectrum_abs(const double* series, long long n, double dt, const double* omega,
                                int n_omega, double* out, hipStream_t s);
+// The fixed device scratch of qhfpe_spectrum_corr_noalloc: kScratchDoubles
+// doubles per device; scratch_pointer() returns the current device's address.
+constexpr size_t kScratchDoubles = size_t(1) << 17;  // 1 MiB
+constexpr int kMaxDevices = 64;
+hipError_t scratch_pointer(double** out);
 hipError_t launch_spectrum_corr(const double* r3, int n1, int n3, double dt1, double dt3,
                                 const double* w1, int nw1, const double* w3, int nw3,
                                 double* work, double* out, hipStream_t s);

@@ -103,6 +103,8 @@ def lib():
         "qhfpe_spectrum_abs": ([_vp, _c_i64, _c_dbl, _vp, _c_i32, _vp, _vp], _c_int),
         "qhfpe_spectrum_corr": ([_vp, _c_i32, _c_i32, _c_dbl, _c_dbl, _vp, _c_i32, _vp, _c_i32, _vp, _vp, _vp],
                                 _c_int),
+        "qhfpe_spectrum_corr_noalloc": ([_vp, _c_i32, _c_i32, _c_dbl, _c_dbl, _vp, _c_i32, _vp, _c_i32, _vp, _vp],
+                                        _c_int),
         "qhfpe_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
