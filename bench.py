@@ -203,9 +203,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-two-d", action="store_true",
                     help="skip the batched 2D spectrum (128x128, depth 6, 64 x 16 delays, 4000 steps)")
-    ap.add_argument("--two-d-graph", action="store_true",
-                    help="run the 2D spectrum's protocol as one recorded graph (record and instantiate "
-                         "reported apart)")
+    ap.add_argument("--two-d-eager", action="store_true",
+                    help="run the 2D spectrum's protocol eagerly instead of as two recorded graphs "
+                         "(preparation, t3 propagation)")
     ap.add_argument("--two-d-scale", type=int, default=1,
                     help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
     ap.add_argument("--paper", action="store_true",
@@ -353,15 +353,25 @@ def main():
         line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
     if not args.no_two_d:
-        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, not args.no_fp64_check_2d, args.two_d_graph)
+        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, not args.no_fp64_check_2d, not args.two_d_eager)
+    # the optional legs report a failure in the line instead of losing it
     if args.sweep:
-        line["uneven_sweep"] = uneven_sweep(args.sweep_steps, args.sweep_streams, args.fp64_check)
+        line["uneven_sweep"] = optional_leg(uneven_sweep, args.sweep_steps, args.sweep_streams, args.fp64_check)
     if args.paper:
-        line["paper_workload"] = paper_workload(args.paper_steps)
+        line["paper_workload"] = optional_leg(paper_workload, args.paper_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline([inputs.model_dict(base, zeta=z) for z in zetas])
         note("cpu baseline done")
     print(json.dumps(line, default=float))
+
+
+def optional_leg(fn, *a):
+    """Run an optional leg; a failure is reported as {"error": ...}."""
+    try:
+        return fn(*a)
+    except Exception as e:  # noqa: BLE001 - reported, not hidden
+        note(f"{fn.__name__} failed: {e}")
+        return dict(error=f"{type(e).__name__}: {e}")
 
 
 def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
@@ -427,7 +437,7 @@ def paper_workload(nsteps: int = 0):
     overdamped (zeta = 400 cm^-1, gamma -> infinity: depth 0, Eq. (heomW))."""
     from paper_1706_09590_amd import inputs
     out = paper_case(inputs.PAPER_ABSORPTION, nsteps)
-    out["overdamped"] = paper_case(inputs.PAPER_OVERDAMPED, nsteps)
+    out["overdamped"] = optional_leg(paper_case, inputs.PAPER_OVERDAMPED, nsteps)
     return out
 
 
@@ -452,18 +462,22 @@ def paper_case(w: dict, nsteps: int = 0):
     out = dict(mesh=f"{m['np']} x {m['nq']} (p x q)", depth=m["depth"], zeta=m["zeta"], rk4_steps=nsteps,
                dt=m["dt"], dt_times_spectral_radius=rho * m["dt"])
     # W_eq: FP64 real-time relaxation of the full hierarchy from the harmonic
-    # thermal state (reported apart)
-    # at the largest stable RK4 step (the stationary state does not depend on it)
+    # thermal state (reported apart), at the largest stable RK4 step (the
+    # stationary state does not depend on it); cases without relaxation start
+    # from the harmonic thermal state itself
     dt_relax = 2.0 / rho
     E = qhfpe.Propagator(inputs.model_dict(m, dt=dt_relax), batch=1, precision="fp64", device=dev)
     E.set_potential_morse_gauss(**surf)
     E.init_thermal(w["thermal_omega"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps, res = E.relax(w["relax_tol"], w["relax_max_steps"], 1000)
-    torch.cuda.synchronize()
-    out.update(equilibration_s=time.perf_counter() - t0, equilibration_steps=steps, equilibration_residual=res,
-               equilibration_dt=dt_relax)
+    if w.get("relax", True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, res = E.relax(w["relax_tol"], w["relax_max_steps"], 1000)
+        torch.cuda.synchronize()
+        out.update(equilibration_s=time.perf_counter() - t0, equilibration_steps=steps,
+                   equilibration_residual=res, equilibration_dt=dt_relax)
+    else:
+        out.update(initial_state="harmonic thermal Wigner function (no relaxation)")
     W_eq = E.get_state()
     E.close()
     spec = {}
@@ -499,10 +513,11 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False)
     traces), and the correlation and transient-absorption spectra on
     [0, 20]^2 (step 0.05).  The t3 propagation is bracketed by HIP events on
     the protocol's stream: its average stage launch gives the roofline
-    (algorithmic bytes 3 n_s^2 w per cell and stage).  graph: the whole
-    protocol is recorded into one graph first (record and instantiate
-    reported apart) and launched.  fp64_check: the same spectra from the
-    FP64 state (untimed), for the FP32 error statement."""
+    (algorithmic bytes 3 n_s^2 w per cell and stage).  graph: the protocol
+    is recorded into two graphs first, the preparation and the t3
+    propagation (record and instantiate reported apart), and launched back
+    to back with the events between them.  fp64_check: the same spectra from
+    the FP64 state (untimed), for the FP32 error statement."""
     import torch
 
     from paper_1706_09590_amd import inputs, response
@@ -535,12 +550,14 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False)
         if graph:
             torch.cuda.synchronize()
             g0 = time.perf_counter()
-            g = pr.record()
-            out["graph"] = dict(record_and_instantiate_s=time.perf_counter() - g0, nodes=g.nodes)
-            note(f"2D spectrum: graph of {g.nodes} nodes recorded")
+            gs = pr.record()
+            nodes = [g.nodes for g in gs]
+            out["graph"] = dict(record_and_instantiate_s=time.perf_counter() - g0, nodes_prep=nodes[0],
+                                nodes_t3=nodes[1])
+            note(f"2D spectrum: graphs of {nodes} nodes recorded")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pr.run(None if graph else ev)
+        pr.run(ev)
         R3 = pr.result()
         Ic, It = spectra(R3)
         torch.cuda.synchronize()
@@ -555,17 +572,18 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False)
                n_t1=len(t1s), n_t2=len(t2s), n3_steps=n3, members=B, cell_updates=updates,
                cell_updates_per_s=updates / (t2 - t1), mode="graph" if graph else "eager",
                finite=bool(torch.isfinite(Ic).all() and torch.isfinite(It).all()))
-    if not graph:
-        t3_s = ev[0].elapsed_time(ev[1]) / 1e3
-        launch_s = t3_s / (4 * n3)
-        nc = m["n_states"] ** 2
-        bpl = 3 * nc * 4 * cells * B  # FP32 state: 3 n_s^2 w per cell and stage
-        bpl_f = 2.5 * nc * 4 * cells * B
-        out["t3_roofline"] = dict(bound="hbm", achieved=round(bpl / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
-                                  unit="GB/s", frac=round(bpl / launch_s / 1e9 / HBM_PEAK_GBS, 4),
-                                  avg_stage_launch_us=round(launch_s * 1e6, 2), bytes_per_stage_launch=bpl,
-                                  frac_factored_bytes=round(bpl_f / launch_s / 1e9 / HBM_PEAK_GBS, 4),
-                                  t3_propagation_s=t3_s)
+    # the t3 propagation: 4 n3 stage launches (plus its small finalisation
+    # kernels) between the two events on the protocol's stream
+    t3_s = ev[0].elapsed_time(ev[1]) / 1e3
+    launch_s = t3_s / (4 * n3)
+    nc = m["n_states"] ** 2
+    bpl = 3 * nc * 4 * cells * B  # FP32 state: 3 n_s^2 w per cell and stage
+    bpl_f = 2.5 * nc * 4 * cells * B
+    out["t3_roofline"] = dict(bound="hbm", achieved=round(bpl / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                              unit="GB/s", frac=round(bpl / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                              avg_stage_launch_us=round(launch_s * 1e6, 2), bytes_per_stage_launch=bpl,
+                              frac_factored_bytes=round(bpl_f / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                              t3_propagation_s=t3_s)
     note(f"2D spectrum: FP32 run {t2 - t1:.1f} s")
     if fp64_check:
         R64 = response.third_order_response(m, W_eq, t1s, t2s, n3, s3, precision="fp64")

@@ -106,7 +106,13 @@ class ThirdOrderProtocol:
 
     def enqueue(self, t3_events=None):
         """t3_events: optional pair of timing events (torch.cuda.Event), recorded
-        on the protocol's stream around the t3 propagation (eager runs only)."""
+        on the protocol's stream around the t3 propagation."""
+        self.enqueue_prep()
+        self.enqueue_t3(t3_events)
+
+    def enqueue_prep(self):
+        """Everything before the t3 propagation: W_eq into A, the t1 and t2
+        propagations and the three excitations."""
         import torch
         A, B1, C = self.A, self.B1, self.C
         n1 = len(self.t1_steps)
@@ -125,25 +131,40 @@ class ThirdOrderProtocol:
                 done = s
                 C.copy_members_from(B1, 0, j * n1, n1)
             C.apply_dipole()
+
+    def enqueue_t3(self, t3_events=None):
+        """The t3 propagation of all members with the trace every stride3 steps."""
+        import torch
+        with torch.cuda.stream(self.stream):
             if t3_events is not None:
                 t3_events[0].record(self.stream)
-            C.step(self.n3_steps, self.stride3, out=self.trace, asynchronous=True)
+            self.C.step(self.n3_steps, self.stride3, out=self.trace, asynchronous=True)
             if t3_events is not None:
                 t3_events[1].record(self.stream)
 
     def record(self):
-        """Record enqueue() into a graph (nothing runs yet)."""
-        self.graph = qhfpe.Graph(self.stream)
-        with self.graph:
-            self.enqueue()
+        """Record the protocol into two graphs launched back to back, the
+        preparation and the t3 propagation (nothing runs yet); timing events
+        can then bracket the t3 graph.  Returns the pair."""
+        prep, t3 = qhfpe.Graph(self.stream), qhfpe.Graph(self.stream)
+        with prep:
+            self.enqueue_prep()
+        with t3:
+            self.enqueue_t3()
+        self.graph = (prep, t3)
         return self.graph
 
     def run(self, t3_events=None):
-        """One pass: the recorded graph if there is one, else eagerly."""
-        if self.graph is not None:
-            self.graph.launch()
-        else:
+        """One pass: the recorded graphs if there are any, else eagerly."""
+        if self.graph is None:
             self.enqueue(t3_events)
+            return
+        self.graph[0].launch()
+        if t3_events is not None:
+            t3_events[0].record(self.stream)
+        self.graph[1].launch()
+        if t3_events is not None:
+            t3_events[1].record(self.stream)
 
     def check(self):
         """Wait for the pass and raise if a trace sample was not finite."""
@@ -158,7 +179,8 @@ class ThirdOrderProtocol:
 
     def close(self):
         if self.graph is not None:
-            self.graph.close()
+            for g in self.graph:
+                g.close()
             self.graph = None
         for P in (self.E, self.A, self.B1, self.C):
             P.close()
