@@ -77,6 +77,9 @@ class Model:
     low_temp_correction: bool = True
     clamp: bool = True              # reading: U(q +- r/2) clamped to the q-grid
     potential_fn: object = None
+    # learned terminator (two states): a linear closure kernel
+    # [13][13][8][4] that replaces Eq. (GMFP) at n = N (see closure_apply)
+    closure: object = None
 
     def __post_init__(self):
         self.poly = np.asarray(self.poly, dtype=np.float64)
@@ -315,6 +318,8 @@ def rhs(m: Model, W: np.ndarray, tables=None) -> np.ndarray:
         f = f + cdelta * d_p2(m, w)
         if n < N:
             f = f + d_p(m, W[n + 1])
+        elif m.closure is not None:
+            f = f + d_p(m, closure_apply(m, w, m.closure))
         else:
             f = f + d_p(m, (r0 / m.mass) * p * w + c0 * d_p(m, w))
         if n >= 1:
@@ -322,6 +327,119 @@ def rhs(m: Model, W: np.ndarray, tables=None) -> np.ndarray:
             f = f + n * m.gamma * ((r0 / m.mass) * p * wl + c0 * d_p(m, wl))
         F[n] = f
     return F
+
+
+# ---------------------------------------------------------------------------
+# Learned terminator (a project addition on top of Eq. (GMFP)): a linear
+# convolution closure W^(N+1) ~ F(W^(N)) over (q, p)
+# ---------------------------------------------------------------------------
+
+CLOSURE_HALF = 6        # offsets -6..6 along q and p (three 5x5 layers)
+CLOSURE_IN = 8          # input channels: the packed components, then p times them
+CLOSURE_OUT = 4         # output channels: the packed components
+
+
+def closure_channels(m: Model, h: np.ndarray) -> np.ndarray:
+    """Input channels of the closure for a two-state Hermitian level h
+    (2, 2, nq, np): the packed components H00, H11, Re H01, Im H01, then the
+    same four multiplied by p.  Returns (8, nq, np) real."""
+    _, p, _ = grids(m)
+    c = np.stack([h[0, 0].real, h[1, 1].real, h[0, 1].real, h[0, 1].imag])
+    return np.concatenate([c, c * p[None, None, :]])
+
+
+def closure_conv(X: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """out[co](q_i, p_a) = sum_{dq, dp, ci} K[dq][dp][ci][co] X[ci](q_{i+dq-6}, p_{a+dp-6}),
+    zero outside the q-grid, periodic in p.  X (ci, nq, np) -> (co, nq, np)."""
+    nci, nq, npp = X.shape
+    H = CLOSURE_HALF
+    out = np.zeros((K.shape[3], nq, npp))
+    for dq in range(2 * H + 1):
+        xs = _shift_q(X, dq - H)
+        for dp in range(2 * H + 1):
+            xsp = np.roll(xs, -(dp - H), axis=-1)   # xsp[..., a] = xs[..., a + dp - H]
+            out += np.einsum('cia,co->oia', xsp, K[dq, dp])
+    return out
+
+
+def closure_apply(m: Model, w: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """The closure F on one complex level w (2, 2, nq, np).  F acts real-
+    linearly on the packed components of a Hermitian level; a general complex
+    level is split as w = H + i G with H, G Hermitian and F(w) = F(H) + i F(G),
+    which makes F complex-linear (as the hierarchy is)."""
+    def packed_to_h(o):
+        h = np.empty((2, 2) + o.shape[1:], dtype=np.complex128)
+        h[0, 0] = o[0]
+        h[1, 1] = o[1]
+        h[0, 1] = o[2] + 1j * o[3]
+        h[1, 0] = o[2] - 1j * o[3]
+        return h
+    wd = np.conj(np.swapaxes(w, 0, 1))
+    H = 0.5 * (w + wd)
+    G = (w - wd) / 2j
+    fH = packed_to_h(closure_conv(closure_channels(m, H), K))
+    fG = packed_to_h(closure_conv(closure_channels(m, G), K))
+    return fH + 1j * fG
+
+
+def analytic_closure_kernel(m: Model) -> np.ndarray:
+    """The kernel whose closure is Eq. (GMFP)'s W^(N+1) = (r_0/m) p W^(N) +
+    c_0 d/dp W^(N) (with the fourth-order periodic d/dp): zeta on the centre
+    tap of the p-channels, c_0 times the d/dp stencil on the plain ones."""
+    r0, c0, _ = bath_constants(m)
+    H = CLOSURE_HALF
+    K = np.zeros((2 * H + 1, 2 * H + 1, CLOSURE_IN, CLOSURE_OUT))
+    for c in range(4):
+        K[H, H, 4 + c, c] = r0 / m.mass
+        for s, w in {-2: 1.0, -1: -8.0, 1: 8.0, 2: -1.0}.items():
+            K[H, H + s, c, c] = c0 * w / (12.0 * m.dp)
+    return K
+
+
+def closure_statistics(m: Model, w_in: np.ndarray, w_out: np.ndarray):
+    """Second-moment statistics of one training pair (level N and level N+1
+    of a Hermitian state, each (2, 2, nq, np)) that define the closure's
+    least-squares loss:
+
+      A[dq][dp][ci][cj] = sum_x X_ci(x) X_cj(x + (dq - 12, dp - 12))    (25 x 25 offsets)
+      C[dq][dp][ci][co] = sum_x X_ci(x + (dq - 6, dp - 6)) Y_co(x)      (13 x 13 offsets)
+      yy = sum_x sum_co Y_co(x)^2
+
+    with X the input channels of w_in and Y the packed components of w_out,
+    zero outside the q-grid and periodic in p."""
+    X = closure_channels(m, w_in)
+    Y = closure_channels(m, w_out)[:4]
+    H2 = 2 * CLOSURE_HALF
+    A = np.zeros((2 * H2 + 1, 2 * H2 + 1, CLOSURE_IN, CLOSURE_IN))
+    for dq in range(2 * H2 + 1):
+        xs = _shift_q(X, dq - H2)
+        for dp in range(2 * H2 + 1):
+            xsp = np.roll(xs, -(dp - H2), axis=-1)
+            A[dq, dp] = np.einsum('cia,dia->cd', X, xsp)
+    H = CLOSURE_HALF
+    C = np.zeros((2 * H + 1, 2 * H + 1, CLOSURE_IN, CLOSURE_OUT))
+    for dq in range(2 * H + 1):
+        xs = _shift_q(X, dq - H)
+        for dp in range(2 * H + 1):
+            xsp = np.roll(xs, -(dp - H), axis=-1)
+            C[dq, dp] = np.einsum('cia,oia->co', xsp, Y)
+    return A, C, float(np.sum(Y * Y))
+
+
+def closure_loss(A: np.ndarray, C: np.ndarray, yy: float, K: np.ndarray) -> float:
+    """sum_x sum_co (F(X) - Y)^2 for the closure kernel K in terms of the
+    statistics, taking sum_x X_ci(x + e) X_cj(x + e') = A[e' - e][ci][cj]
+    (exact when X vanishes within 12 rows of the q edges)."""
+    H, H2 = CLOSURE_HALF, 2 * CLOSURE_HALF
+    n = 2 * H + 1
+    quad = 0.0
+    for e1q in range(n):
+        for e1p in range(n):
+            for e2q in range(n):
+                for e2p in range(n):
+                    a = A[e2q - e1q + H2, e2p - e1p + H2]
+                    quad += np.einsum('co,cd,do->', K[e1q, e1p], a, K[e2q, e2p])
+    return float(quad - 2.0 * np.sum(K * C) + yy)
 
 
 def rk4_step(m: Model, W: np.ndarray, dt: float | None = None, tables=None) -> np.ndarray:

@@ -706,3 +706,87 @@ def test_deep_hierarchy_with_a_strong_cold_bath_grows():
     assert amp(6, 4.0, 2.9) > 100.0
     assert amp(2, 4.0, 2.9) < 10.0
     assert amp(6, 0.5, 1.0) < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Learned terminator (a project addition replacing Eq. (GMFP) at n = N)
+# ---------------------------------------------------------------------------
+
+def _closure_model(nq=20, np_=16, depth=2):
+    d = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], nq=nq, np=np_, depth=depth)
+    return oracle_model(d)
+
+
+def test_closure_with_the_analytic_kernel_is_the_gmfp_terminator():
+    """With the kernel of Eq. (GMFP) (zeta on the centre tap of the
+    p-channels, c0 times the d/dp stencil on the plain channels) the closure
+    RHS equals the plain RHS, for a non-Hermitian state too."""
+    m = _closure_model()
+    W = inputs.random_hierarchy(m.depth, 2, m.nq, m.np_, seed=41) + \
+        0.3j * inputs.random_hierarchy(m.depth, 2, m.nq, m.np_, seed=42)
+    ref = O.rhs(m, W)
+    m.closure = O.analytic_closure_kernel(m)
+    got = O.rhs(m, W)
+    np.testing.assert_allclose(got, ref, atol=1e-12 * np.max(np.abs(ref)))
+    # only the terminator level changes with another kernel
+    m.closure = m.closure + 0.01 * np.random.default_rng(1).standard_normal(m.closure.shape)
+    got2 = O.rhs(m, W)
+    np.testing.assert_array_equal(got2[:-1], got[:-1])
+    assert np.max(np.abs(got2[-1] - got[-1])) > 1e-3
+
+
+def test_closure_convolution_by_direct_summation():
+    """closure_conv against its definition evaluated point by point (zero
+    outside the q-grid, periodic in p) on a tiny grid."""
+    rng = np.random.default_rng(5)
+    nq, npp = 9, 7
+    X = rng.standard_normal((8, nq, npp))
+    K = rng.standard_normal((13, 13, 8, 4))
+    got = O.closure_conv(X, K)
+    ref = np.zeros((4, nq, npp))
+    for i in range(nq):
+        for a in range(npp):
+            for dq in range(13):
+                qi = i + dq - 6
+                if qi < 0 or qi >= nq:
+                    continue
+                for dp in range(13):
+                    pa = (a + dp - 6) % npp
+                    ref[:, i, a] += X[:, qi, pa] @ K[dq, dp]
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_closure_is_complex_linear_and_keeps_hermiticity():
+    m = _closure_model(nq=12, np_=8, depth=0)
+    K = np.random.default_rng(6).standard_normal((13, 13, 8, 4))
+    w1 = inputs.random_hierarchy(0, 2, m.nq, m.np_, seed=7)[0]
+    w2 = inputs.random_hierarchy(0, 2, m.nq, m.np_, seed=8, phase=1)[0]
+    a, b = 0.7 - 0.2j, -1.3 + 0.9j
+    lhs = O.closure_apply(m, a * w1 + b * w2, K)
+    rhs = a * O.closure_apply(m, w1, K) + b * O.closure_apply(m, w2, K)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-10)
+    f = O.closure_apply(m, w1, K)                     # Hermitian in, Hermitian out
+    np.testing.assert_allclose(f, np.conj(np.swapaxes(f, 0, 1)), atol=1e-12)
+    g = O.closure_apply(m, w2, K)                     # i x Hermitian in, i x Hermitian out
+    np.testing.assert_allclose(g, -np.conj(np.swapaxes(g, 0, 1)), atol=1e-12)
+
+
+def test_closure_statistics_give_the_squared_error():
+    """The least-squares loss written through the statistics A, C, yy equals
+    the squared error of the closure computed directly, for data that vanish
+    within 12 rows of the q edges."""
+    m = _closure_model(nq=40, np_=16, depth=0)
+    rng = np.random.default_rng(9)
+
+    def blob(seed):
+        w = inputs.random_hierarchy(0, 2, m.nq, m.np_, seed=seed)[0]
+        w[:, :, :13] = 0.0
+        w[:, :, -13:] = 0.0
+        return w
+    w_in, w_out = blob(10), blob(11)
+    A, C, yy = O.closure_statistics(m, w_in, w_out)
+    K = 0.05 * rng.standard_normal((13, 13, 8, 4))
+    direct = np.sum((O.closure_conv(O.closure_channels(m, w_in), K) - O.closure_channels(m, w_out)[:4]) ** 2)
+    assert O.closure_loss(A, C, yy, K) == pytest.approx(direct, rel=1e-10)
+    # symmetry of the autocorrelation: A[-d][cj][ci] = A[d][ci][cj]
+    np.testing.assert_allclose(A[::-1, ::-1].transpose(0, 1, 3, 2), A, atol=1e-10)
