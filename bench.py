@@ -211,6 +211,9 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
     ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
+    ap.add_argument("--closure", action="store_true",
+                    help="also train the learned terminator on depth-10 runs of the 2D protocol and compare the "
+                         "depth-3 + closure 2D spectra with plain depth 3 and plain depth 10")
     ap.add_argument("--sweep-streams", type=int, default=1, help="batches of the sweep run concurrently")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
@@ -359,10 +362,68 @@ def main():
         line["uneven_sweep"] = optional_leg(uneven_sweep, args.sweep_steps, args.sweep_streams, args.fp64_check)
     if args.paper:
         line["paper_workload"] = optional_leg(paper_workload, args.paper_steps)
+    if args.closure:
+        line["learned_closure"] = optional_leg(learned_closure)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline([inputs.model_dict(base, zeta=z) for z in zetas])
         note("cpu baseline done")
     print(json.dumps(line, default=float))
+
+
+def learned_closure():
+    """The learned terminator on the 2D-spectrum workload (128 x 128): its
+    statistics from 512 depth-10 runs of the 2D protocol (t1 every 20 steps x
+    16 waiting times, 4000 t3 steps, pairs of levels 3 and 4 every 250
+    steps), training, then the full 2D spectrum (64 x 16 x 4000) at depth 3 +
+    closure, plain depth 3 and plain depth 10 (FP32 state, recorded graphs),
+    with the spectral errors against plain depth 10 and the wall times; and
+    the plain FP64 single-trajectory path (one depth-10 t3 propagation per
+    member, timed on one member and multiplied by the member count)."""
+    import numpy as np
+    import torch
+
+    from paper_1706_09590_amd import closure, inputs, response
+    w = inputs.TWO_D_SPECTRUM
+    m = w["model"]
+    m10, m3 = inputs.model_dict(m, depth=10), inputs.model_dict(m, depth=3)
+    t1s, t2s, n3 = w["t1_steps"], w["t2_steps"], w["n3_steps"]
+    om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
+    out = dict(train_depth=10, closed_depth=3, ridge=closure.RIDGE)
+    t0 = time.perf_counter()
+    W10, _, _ = response.equilibrate(m10, tol=1e-10, max_steps=200000, check_every=500, dt=response.relax_step(m10))
+    stats, planes = closure.training_statistics(m10, W10, t1s[::2], t2s, n3, 250, 3)
+    torch.cuda.synchronize()
+    out.update(training_runs=len(t1s[::2]) * len(t2s), training_planes=planes,
+               statistics_s=time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    K, loss = closure.train(stats, m3, iters=3000)
+    out.update(train_s=time.perf_counter() - t0, train_data_loss=loss,
+               gmfp_data_loss=qhfpe_loss(stats, closure.gmfp_kernel(m3)))
+    note(f"closure trained: loss {loss:.3e}")
+
+    def err(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+    I10c, I10t, w10, e10 = closure.two_d_spectra(m10, t1s, t2s, n3, om)
+    I3c, I3t, w3, e3 = closure.two_d_spectra(m3, t1s, t2s, n3, om)
+    Icc, Ict, wc, ec = closure.two_d_spectra(m3, t1s, t2s, n3, om, closure=K)
+    out.update(plain10_wall_s=w10, plain3_wall_s=w3, closure3_wall_s=wc,
+               plain3_corr_err=err(I3c, I10c), plain3_tas_err=err(I3t, I10t),
+               closure3_corr_err=err(Icc, I10c), closure3_tas_err=err(Ict, I10t),
+               finite=bool(torch.isfinite(Icc).all() and torch.isfinite(Ict).all()))
+    one = closure.single_trajectory_seconds(m10, n3, precision="fp64")
+    B = len(t1s) * len(t2s)
+    out.update(fp64_single_trajectory_s=one, fp64_single_trajectory_path_s_extrapolated=one * B,
+               speedup_vs_fp64_single_trajectory=one * B / wc, speedup_vs_plain10_batched=w10 / wc)
+    note("closure comparison done")
+    del np
+    return out
+
+
+def qhfpe_loss(stats, kernel):
+    import torch
+
+    from paper_1706_09590_amd import qhfpe
+    return qhfpe.closure_loss(stats, torch.from_numpy(kernel).to(stats.device))
 
 
 def optional_leg(fn, *a):

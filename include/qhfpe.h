@@ -265,6 +265,84 @@ int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every,
 int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst,
                        int32_t dst_member, int32_t count);
 
+/* Learned hierarchy terminator (two states, np = 128 or 256).  In place of
+ * Eq. (GMFP), which closes the hierarchy with W^(N+1) ~ (zeta p + c0 d/dp)
+ * W^(N), a linear convolution F over (q, p) predicts W^(N+1) from W^(N):
+ *   F(W)_co(q_i, p_a) = sum_{dq, dp, ci} K[dq][dp][ci][co] X_ci(q_{i+dq-6}, p_{a+dp-6}),
+ * dq, dp = 0..12, X = (the packed components H00, H11, Re H01, Im H01 of
+ * W^(N), then the same four times p), zero outside the q grid, periodic in p;
+ * the output channels are the packed components of W^(N+1).  F acts on the
+ * Hermitian part of each member's state (the phase i^k factors out, F being
+ * linear).  K is the composition of three 5x5 layers 8 -> 32 -> 32 -> 4
+ * without biases or activations (a closure of a linear equation is linear),
+ * trained by gradient descent (qhfpe_closure_train) on second-moment
+ * statistics of deep-hierarchy runs (qhfpe_closure_stats).  The analytic
+ * closure is one such K, so the learned one can only improve the fit. */
+enum {
+  QHFPE_CLOSURE_KERNEL_FLOATS = 13 * 13 * 8 * 4,          /* K[13][13][8][4] */
+  QHFPE_CLOSURE_STATS_DOUBLES = 25 * 25 * 8 * 8 + 13 * 13 * 8 * 4 + 1,
+  QHFPE_CLOSURE_TRAIN_FLOATS = 203906
+};
+
+/* Accumulate (+=) into d_stats the statistics of the training pairs
+ * (level, level + 1) of every member's current state, FP64:
+ *   A[dq][dp][ci][cj] = sum_x X_ci(x) X_cj(x + (dq - 12, dp - 12)),  dq, dp = 0..24,
+ *   C[dq][dp][ci][co] = sum_x X_ci(x + (dq - 6, dp - 6)) Y_co(x),      dq, dp = 0..12,
+ *   yy = sum_x sum_co Y_co(x)^2,
+ * stored in that order (X of level `level`, Y the packed level + 1; zero
+ * outside the q grid, periodic in p).  The caller zeroes d_stats
+ * (QHFPE_CLOSURE_STATS_DOUBLES) before the first call.  0 <= level < depth.
+ * Asynchronous. */
+int qhfpe_closure_stats(qhfpe_t* h, int32_t level, double* d_stats);
+
+/* The kernel K whose closure is Eq. (GMFP), W^(N+1) = zeta p W^(N) +
+ * c0 d/dp W^(N) (fourth-order periodic d/dp), for the handle's bath and grid
+ * (the params' zeta, gamma, beta): h_kernel[QHFPE_CLOSURE_KERNEL_FLOATS]
+ * (host).  The prior of qhfpe_closure_train. */
+int qhfpe_closure_gmfp_kernel(const qhfpe_t* h, float* h_kernel);
+
+/* Train the three layers by Adam (iters steps, learning rate decaying
+ * geometrically from lr to lr_final, seeded uniform initial layers) on
+ *   [ sum (F(X) - Y)^2 + ridge * d * ||K - K0||^2 ] / yy,
+ * written through d_stats (in which sum_x X(x + e) X(x + e') is A[e' - e],
+ * exact for states that vanish within 12 rows of the q edges), with d the
+ * mean zero-offset channel energy (1/8) sum_c A[12][12][c][c] and K0 = d_prior
+ * (device FP32 kernel, e.g. qhfpe_closure_gmfp_kernel; NULL = 0).  The ridge
+ * term keeps the taps the data do not determine at the prior: a closure fit
+ * to the data alone can give the closed hierarchy growing modes.  With a
+ * prior the layers start at it (identity through the centre taps of the
+ * first two layers, the prior's central 5 x 5 taps in the third; taps of the
+ * prior outside them are dropped), plus seeded weights of 1e-3 of that
+ * scale; without one from the seeded weights alone.  d_state:
+ * QHFPE_CLOSURE_TRAIN_FLOATS of device scratch (layers, gradients,
+ * moments).  d_kernel receives the composite K (FP32,
+ * QHFPE_CLOSURE_KERNEL_FLOATS), h_loss (may be NULL) its normalised data
+ * loss sum (F(X) - Y)^2 / yy.  Runs on stream; synchronous. */
+int qhfpe_closure_train(const double* d_stats, const float* d_prior, double ridge, float* d_state, uint64_t seed,
+                        int32_t iters, double lr, double lr_final, float* d_kernel, double* h_loss, void* stream);
+
+/* The normalised data loss sum (F(X) - Y)^2 / yy of the kernel d_kernel
+ * (device FP32) on the statistics d_stats, into *h_loss; d_state: device
+ * scratch of QHFPE_CLOSURE_TRAIN_FLOATS (its layers are not touched).  Runs
+ * on stream; synchronous. */
+int qhfpe_closure_loss(const double* d_stats, const float* d_kernel, float* d_state, double* h_loss, void* stream);
+
+/* Bytes of the device buffer qhfpe_set_closure needs for these parameters
+ * (the BF16 weights and the predicted level of every member).  Host call. */
+int qhfpe_closure_buffer_bytes(const qhfpe_params* params, size_t* bytes);
+
+/* Use the closure K (device FP32 K[13][13][8][4], read during this call) at
+ * the deepest level of every later stage (qhfpe_step, qhfpe_apply_rhs,
+ * qhfpe_residual, qhfpe_relax): before each stage the library evaluates
+ * F(W^(N)) of the stage input with BF16 inputs and weights on the matrix
+ * cores (FP32 accumulation) into d_buffer (256-byte aligned, at least
+ * qhfpe_closure_buffer_bytes, kept alive while the closure is set: the BF16
+ * weights, 57344 bytes, then the predicted levels [B][4][nq][np] in the
+ * state precision), and the stage uses it as W^(N+1) (no Eq. (GMFP) terms).  d_kernel = NULL switches
+ * back to Eq. (GMFP).  The wave variant only (QHFPE_EUNSUPPORTED otherwise);
+ * the handle switches to it.  Asynchronous. */
+int qhfpe_set_closure(qhfpe_t* h, const float* d_kernel, void* d_buffer, size_t bytes);
+
 /* Device-to-device copy of bytes (d_dst, d_src 16-byte aligned, ranges
  * not overlapping) by the library's streaming kernel: 16-byte loads and
  * stores per lane, every lane's loads issued before its stores.  It is the

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqhfpe.so")
 
-SOURCES = ["qhfpe_api.cpp", "aux_kernels.hip", "stage_f64_ns2.hip", "stage_f64_ns3.hip",
+SOURCES = ["qhfpe_api.cpp", "aux_kernels.hip", "closure.hip", "stage_f64_ns2.hip", "stage_f64_ns3.hip",
            "stage_f32_ns2.hip", "stage_f32_ns3.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -311,6 +311,10 @@ struct qhfpe_handle {
   // false until a state is loaded (set_state, init_thermal, copy_members):
   // a partial copy may then set the phase of the (all-zero) state
   bool loaded = false;
+  // learned terminator (qhfpe_set_closure): BF16 weights in the MFMA layout
+  // and the closure's W^(N+1) [B][level], in the caller's buffer
+  unsigned short* closure_wb = nullptr;
+  void* closure_out = nullptr;
 
   ~qhfpe_handle() {
     for (int g = 0; g < groups_made; ++g) {
@@ -401,6 +405,7 @@ struct qhfpe_handle {
     a.qcoup = qcoup;
     a.bath = bath();
     a.psym = psym();
+    a.closure = closure_out;
     a.slot = 0;
     a.nq = p.nq;
     a.depth = p.depth;
@@ -436,6 +441,7 @@ struct qhfpe_handle {
     a.v = static_cast<const char*>(a.v) + off;
     if (a.y) a.y = static_cast<const char*>(a.y) + off;
     a.out = static_cast<char*>(a.out) + off;
+    if (a.closure) a.closure = static_cast<const char*>(a.closure) + (size_t)first * L.level_elems * L.elem;
     a.bath += (long long)kBathStride * first;
     if (a.partials) a.partials += (long long)first * kRespSlots * a.ntiles;
     a.batch = count;
@@ -447,6 +453,13 @@ struct qhfpe_handle {
 
   hipError_t launch_on(const StageArgs& a, hipStream_t s) const {
     const int nblocks = a.nblocks_padded;
+    if (a.closure) {
+      // the learned W^(N+1) of this stage's input, for these members
+      hipError_t e = launch_closure_apply(p.precision, p.np, a.v, p.depth, L.member_elems, L.level_elems,
+                                          L.comp_elems, p.nq, a.batch, p.p_min, dp, closure_wb,
+                                          const_cast<void*>(a.closure), L.level_elems, s);
+      if (e != hipSuccess) return e;
+    }
     if (wave())
       return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(p.np, a, nblocks, s)
                                        : launch_stage_wave_f32(p.np, a, nblocks, s);
@@ -457,6 +470,10 @@ struct qhfpe_handle {
                    : launch_stage_f32_ns3(p.np, cpt, a, nblocks, s);
   }
 };
+
+static_assert(QHFPE_CLOSURE_KERNEL_FLOATS == kClosureKernelElems, "closure kernel size");
+static_assert(QHFPE_CLOSURE_STATS_DOUBLES == kClosureStatsSize, "closure statistics size");
+static_assert(QHFPE_CLOSURE_TRAIN_FLOATS == ClosureTrainLayout::total, "closure training state size");
 
 struct qhfpe_graph {
   hipGraph_t graph = nullptr;
@@ -693,6 +710,8 @@ int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
   if (h->qcoup && c != kTileWave)
     return fail(QHFPE_EUNSUPPORTED, "a q-dependent coupling needs the wave variant (tile 1)");
+  if (h->closure_out && c != kTileWave)
+    return fail(QHFPE_EUNSUPPORTED, "a learned closure needs the wave variant (tile 1)");
   h->cpt = c;
   return QHFPE_OK;
 }
@@ -714,7 +733,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   int rc = QHFPE_OK;
   for (int c : candidates) {
     if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c)) continue;
-    if (h->qcoup && c != kTileWave) continue;
+    if ((h->qcoup || h->closure_out) && c != kTileWave) continue;
     h->cpt = c;
     StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
     hipError_t e = h->launch(a);  // warm-up
@@ -1067,6 +1086,146 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int
   }
   dst->phase = src->phase;
   dst->loaded = true;
+  return QHFPE_OK;
+}
+
+int qhfpe_closure_loss(const double* d_stats, const float* d_kernel, float* d_state, double* h_loss, void* stream) {
+  if (!d_stats || !d_kernel || !d_state || !h_loss) return fail(QHFPE_EINVAL, "NULL pointer");
+  using TL = ClosureTrainLayout;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* d_loss = reinterpret_cast<double*>(d_state + TL::loss);
+  HIP_TRY(launch_closure_loss(d_stats, d_kernel, d_state + TL::gk, reinterpret_cast<double*>(d_state + TL::terms),
+                              d_loss, s));
+  HIP_TRY(hipMemcpyAsync(h_loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return QHFPE_OK;
+}
+
+int qhfpe_closure_buffer_bytes(const qhfpe_params* params, size_t* bytes) {
+  if (!bytes) return fail(QHFPE_EINVAL, "bytes is NULL");
+  if (int rc = validate(params)) return rc;
+  const Layout L = make_layout(params);
+  *bytes = align_up((size_t)kClosureWeightElems * sizeof(unsigned short)) +
+           align_up((size_t)L.level_elems * params->batch * L.elem);
+  return QHFPE_OK;
+}
+
+int qhfpe_set_closure(qhfpe_t* h, const float* d_kernel, void* d_buffer, size_t bytes) {
+  if (int rc = check_handle(h)) return rc;
+  if (!d_kernel) {
+    h->closure_wb = nullptr;
+    h->closure_out = nullptr;
+    return QHFPE_OK;
+  }
+  if (!wave_supported(h->ns, h->p.np))
+    return fail(QHFPE_EUNSUPPORTED, "a learned closure needs two states and np = 128 or 256");
+  if (!d_buffer || reinterpret_cast<uintptr_t>(d_buffer) % kAlign)
+    return fail(QHFPE_EINVAL, "d_buffer must be a 256-byte aligned device buffer");
+  size_t need = 0;
+  if (int rc = qhfpe_closure_buffer_bytes(&h->p, &need)) return rc;
+  if (bytes < need) return fail(QHFPE_ESTATE, "closure buffer too small: %zu < %zu bytes", bytes, need);
+  unsigned short* wb = static_cast<unsigned short*>(d_buffer);
+  HIP_TRY(launch_closure_weights(d_kernel, wb, h->stream));
+  h->closure_wb = wb;
+  h->closure_out = static_cast<char*>(d_buffer) + align_up((size_t)kClosureWeightElems * sizeof(unsigned short));
+  h->cpt = kTileWave;
+  return QHFPE_OK;
+}
+
+int qhfpe_closure_stats(qhfpe_t* h, int32_t level, double* d_stats) {
+  if (int rc = check_handle(h)) return rc;
+  if (!d_stats) return fail(QHFPE_EINVAL, "d_stats is NULL");
+  if (!wave_supported(h->ns, h->p.np))
+    return fail(QHFPE_EUNSUPPORTED, "closure statistics need two states and np = 128 or 256");
+  if (level < 0 || level >= h->p.depth) return fail(QHFPE_EINVAL, "need 0 <= level < depth (level + 1 is the target)");
+  HIP_TRY(launch_closure_stats(h->p.precision, h->p.np, h->y(), level, h->L.member_elems, h->L.level_elems,
+                               h->L.comp_elems, h->p.nq, h->p.batch, h->p.p_min, h->dp, d_stats, h->stream));
+  return QHFPE_OK;
+}
+
+int qhfpe_closure_gmfp_kernel(const qhfpe_t* h, float* h_kernel) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h_kernel) return fail(QHFPE_EINVAL, "h_kernel is NULL");
+  if (h->ns != 2) return fail(QHFPE_EUNSUPPORTED, "the closure is defined for two states");
+  double bc[kBathStride];
+  bath_constants(h->p, h->p.zeta, h->p.gamma, h->p.beta, bc);
+  const double zeta = bc[0], c0 = bc[2];
+  constexpr int S = 2 * kClosureHalf + 1;
+  for (int e = 0; e < kClosureKernelElems; ++e) h_kernel[e] = 0.0f;
+  auto at = [&](int dq, int dp, int ci, int co) -> float& {
+    return h_kernel[((dq * S + dp) * kClosureIn + ci) * kClosureOut + co];
+  };
+  // W^(N+1) = zeta p W^(N) + c0 D_p W^(N), D_p the periodic fourth-order stencil
+  const double w[5] = {1.0, -8.0, 0.0, 8.0, -1.0};  // taps p - 2 .. p + 2, times 1 / (12 dp)
+  for (int c = 0; c < 4; ++c) {
+    at(kClosureHalf, kClosureHalf, 4 + c, c) = (float)zeta;
+    for (int s = -2; s <= 2; ++s)
+      if (s != 0) at(kClosureHalf, kClosureHalf + s, c, c) = (float)(c0 * w[s + 2] / (12.0 * h->dp));
+  }
+  return QHFPE_OK;
+}
+
+int qhfpe_closure_train(const double* d_stats, const float* d_prior, double ridge, float* d_state, uint64_t seed,
+                        int32_t iters, double lr, double lr_final, float* d_kernel, double* h_loss, void* stream) {
+  if (!d_stats || !d_state || !d_kernel) return fail(QHFPE_EINVAL, "NULL pointer");
+  if (iters < 0 || !(lr > 0) || !(lr_final > 0)) return fail(QHFPE_EINVAL, "need iters >= 0, lr > 0, lr_final > 0");
+  if (!(ridge >= 0) || !std::isfinite(ridge)) return fail(QHFPE_EINVAL, "ridge must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  using TL = ClosureTrainLayout;
+  // seeded initial layers (uniform, variance 1 / fan-in: the composite of the
+  // three layers starts at the scale of its inputs); zero Adam moments
+  std::vector<float> init((size_t)TL::total, 0.0f);
+  uint64_t x = seed;
+  auto next = [&]() {  // splitmix64
+    x += 0x9e3779b97f4a7c15ULL;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+  };
+  auto fill = [&](int off, int n, int fan_in) {
+    const double a = std::sqrt(3.0 / fan_in);
+    for (int i = 0; i < n; ++i) init[off + i] = (float)(a * (2.0 * ((next() >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+  };
+  fill(TL::w1, TL::n1, 25 * kClosureIn);
+  fill(TL::w2, TL::n2, 25 * kClosureHidden);
+  fill(TL::w3, TL::n3, 25 * kClosureHidden);
+  if (d_prior) {
+    // start at the prior: the first two layers pass the 8 input channels
+    // through their centre taps (identity into hidden channels 0..7), the
+    // third holds the prior's central 5 x 5 taps; the random weights stay,
+    // scaled down, to break the symmetry of the hidden channels
+    std::vector<float> k0(kClosureKernelElems);
+    HIP_TRY(hipMemcpyAsync(k0.data(), d_prior, k0.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < TL::nparam; ++i) init[i] *= 1e-3f;
+    constexpr int H = kClosureHidden, S = 2 * kClosureHalf + 1;
+    for (int c = 0; c < kClosureIn; ++c) {
+      init[TL::w1 + (12 * kClosureIn + c) * H + c] = 1.0f;  // tap (2, 2) is the centre of 5 x 5
+      init[TL::w2 + (12 * H + c) * H + c] = 1.0f;
+    }
+    for (int tq = 0; tq < 5; ++tq)
+      for (int tp = 0; tp < 5; ++tp)
+        for (int c = 0; c < kClosureIn; ++c)
+          for (int o = 0; o < kClosureOut; ++o)
+            init[TL::w3 + ((tq * 5 + tp) * H + c) * kClosureOut + o] =
+                k0[(((tq + kClosureHalf - 2) * S + (tp + kClosureHalf - 2)) * kClosureIn + c) * kClosureOut + o];
+  }
+  HIP_TRY(hipMemcpyAsync(d_state, init.data(), init.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  for (int t = 1; t <= iters; ++t) {
+    // learning rate decays geometrically from lr to lr_final
+    const double f = iters > 1 ? (double)(t - 1) / (iters - 1) : 0.0;
+    const float lr_t = (float)(lr * std::pow(lr_final / lr, f));
+    HIP_TRY(launch_closure_train_step(d_stats, d_prior, ridge, d_state, t, lr_t, nullptr, s));
+  }
+  // the composite kernel of the final layers and its normalised loss
+  double* d_loss = reinterpret_cast<double*>(d_state + TL::loss);
+  HIP_TRY(launch_closure_compose(d_stats, d_state, d_loss, s));
+  HIP_TRY(hipMemcpyAsync(d_kernel, d_state + TL::k, kClosureKernelElems * sizeof(float), hipMemcpyDeviceToDevice, s));
+  double loss = 0.0;
+  HIP_TRY(hipMemcpyAsync(&loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h_loss) *h_loss = loss;
   return QHFPE_OK;
 }
 

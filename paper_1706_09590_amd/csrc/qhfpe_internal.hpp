@@ -74,6 +74,7 @@ struct StageArgs {
                          // U_01(q - r/2) (both / (hbar np)), entry (k1, k2) at m = k1 + n1 k2
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
+  const void* closure;   // wave variant: learned W^(N+1) [B][4][nq][np] (one level per member), or nullptr
   int slot;
   int qcoup;  // 1: q-dependent coupling through the r-space multiply (wave variant, two states)
   int nq;
@@ -90,6 +91,52 @@ struct StageArgs {
   double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];     // off-diagonal couplings / hbar
   double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
 };
+
+// Learned terminator (closure.hip): a linear 13x13 convolution over (q, p)
+// from 8 input channels (the packed components of level N and the same times
+// p) to the 4 packed components of level N + 1, trained as three 5x5 layers
+// with kClosureHidden channels.
+constexpr int kClosureHalf = 6;
+constexpr int kClosureIn = 8;
+constexpr int kClosureOut = 4;
+constexpr int kClosureHidden = 32;
+constexpr int kClosureKernelElems = 13 * 13 * kClosureIn * kClosureOut;   // K[13][13][8][4]
+constexpr int kClosureStatsA = 25 * 25 * kClosureIn * kClosureIn;         // A[25][25][8][8]
+constexpr int kClosureStatsC = 13 * 13 * kClosureIn * kClosureOut;        // C[13][13][8][4]
+constexpr int kClosureStatsSize = kClosureStatsA + kClosureStatsC + 1;    // + yy
+constexpr int kClosureWeightElems = 16 * 7 * 16 * 16;                     // BF16 MFMA B layout
+// Training state (floats): the three layers, their gradients, Adam moments,
+// the 9x9 product of the first two layers and its gradient, the composite
+// kernel and its gradient, and per-entry loss terms (doubles).
+struct ClosureTrainLayout {
+  static constexpr int w1 = 0, n1 = 25 * kClosureIn * kClosureHidden;
+  static constexpr int w2 = w1 + n1, n2 = 25 * kClosureHidden * kClosureHidden;
+  static constexpr int w3 = w2 + n2, n3 = 25 * kClosureHidden * kClosureOut;
+  static constexpr int nparam = n1 + n2 + n3;
+  static constexpr int g1 = nparam, g2 = g1 + n1, g3 = g2 + n2;
+  static constexpr int m = 2 * nparam, v = 3 * nparam;
+  static constexpr int w12 = 4 * nparam, n12 = 81 * kClosureIn * kClosureHidden;
+  static constexpr int g12 = w12 + n12;
+  static constexpr int k = g12 + n12;
+  static constexpr int gk = k + kClosureKernelElems;
+  static constexpr int terms = gk + kClosureKernelElems;  // kClosureKernelElems doubles
+  static constexpr int loss = terms + 2 * kClosureKernelElems;  // one double
+  static constexpr int total = loss + 2;
+};
+static_assert(ClosureTrainLayout::terms % 2 == 0 && ClosureTrainLayout::loss % 2 == 0, "doubles stay aligned");
+
+hipError_t launch_closure_weights(const float* K, unsigned short* wb, hipStream_t s);
+hipError_t launch_closure_apply(int precision, int np, const void* v, int level, long long member_stride,
+                                long long level_stride, long long comp_stride, int nq, int batch, double p0,
+                                double dp, const unsigned short* wb, void* out, long long out_stride, hipStream_t s);
+hipError_t launch_closure_stats(int precision, int np, const void* v, int level, long long member_stride,
+                                long long level_stride, long long comp_stride, int nq, int batch, double p0,
+                                double dp, double* stats, hipStream_t s);
+hipError_t launch_closure_train_step(const double* stats, const float* prior, double ridge, float* state, int t,
+                                     float lr, double* loss, hipStream_t s);
+hipError_t launch_closure_compose(const double* stats, float* state, double* loss, hipStream_t s);
+hipError_t launch_closure_loss(const double* stats, const float* K, float* g, double* terms, double* loss,
+                               hipStream_t s);
 
 // Host launchers (one translation unit per precision and state count).
 hipError_t launch_stage_f64_ns2(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);

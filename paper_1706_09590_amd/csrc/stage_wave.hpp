@@ -120,8 +120,12 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   // ghost columns beyond the q edges (their offsets are set past every
   // level), v^(n+1) at n = N, v^(n-1) at n = 0 and a missing y.
   const bool has_up = n < a.depth, has_dn = n >= 1;
+  // learned terminator: at n = N the level above is the closure's W^(N+1)
+  const bool clos = a.closure != nullptr && !has_up;
   const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);
-  const rsrc_t ru = make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, has_up ? level_bytes : 0u);
+  const rsrc_t ru =
+      clos ? make_rsrc(static_cast<const T*>(a.closure) + (long long)b * a.level_stride, level_bytes)
+           : make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, has_up ? level_bytes : 0u);
   const rsrc_t rd = make_rsrc(vm + (long long)(has_dn ? n - 1 : n) * a.level_stride, has_dn ? level_bytes : 0u);
   const bool has_y = a.y != nullptr;
   const rsrc_t ry = make_rsrc(has_y ? static_cast<const T*>(a.y) + (long long)b * a.member_stride +
@@ -166,7 +170,8 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   }
   const T dpinv = T(1.0 / (12.0 * a.dp));
   // the terminator level differentiates zeta p v^(N) in place of v^(N+1)
-  const T zterm = has_up ? T(0) : zeta;
+  // (Eq. (GMFP)), unless a learned closure supplies W^(N+1)
+  const T zterm = (has_up || clos) ? T(0) : zeta;
 
   // ---- local terms, one component at a time ------------------------------
   // v^(n) at the task columns is the middle of the kinetic window, so it is
@@ -399,7 +404,7 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   // r-space multiplication (position k2 + (N2+1) k1 holds index
   // m = k1 + N1 k2) and the first inverse pass; every lane reads its own and
   // its partner rows before any lane writes
-  const T c0t = has_up ? T(0) : c0;  // terminator level carries c0 D_p D_p
+  const T c0t = (has_up || clos) ? T(0) : c0;  // terminator level carries c0 D_p D_p
   cx<T> yk[I2][N2];
 #pragma unroll
   for (int t = 0; t < I2; ++t) {

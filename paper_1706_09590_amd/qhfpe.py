@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_PKG, "libqhfpe.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "qhfpe.h")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+CLOSURE_KERNEL_FLOATS = 13 * 13 * 8 * 4
+CLOSURE_STATS_DOUBLES = 25 * 25 * 8 * 8 + 13 * 13 * 8 * 4 + 1
+CLOSURE_TRAIN_FLOATS = 203906
 FP64, FP32_FP64RED = 0, 1
 COMMUTATOR = 0
 MAX_STATES = 3
@@ -105,6 +108,13 @@ def lib():
                                 _c_int),
         "qhfpe_spectrum_corr_noalloc": ([_vp, _c_i32, _c_i32, _c_dbl, _c_dbl, _vp, _c_i32, _vp, _c_i32, _vp, _vp],
                                         _c_int),
+        "qhfpe_closure_stats": ([_vp, _c_i32, _vp], _c_int),
+        "qhfpe_closure_train": ([_vp, _vp, _c_dbl, _vp, ctypes.c_uint64, _c_i32, _c_dbl, _c_dbl, _vp,
+                                 ctypes.POINTER(_c_dbl), _vp], _c_int),
+        "qhfpe_closure_gmfp_kernel": ([_vp, _vp], _c_int),
+        "qhfpe_closure_loss": ([_vp, _vp, _vp, ctypes.POINTER(_c_dbl), _vp], _c_int),
+        "qhfpe_closure_buffer_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], _c_int),
+        "qhfpe_set_closure": ([_vp, _vp, _vp, ctypes.c_size_t], _c_int),
         "qhfpe_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -337,6 +347,70 @@ class Propagator:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    # -- learned terminator ---------------------------------------------------
+    def closure_stats(self, level: int, stats):
+        """Accumulate the closure statistics of (level, level + 1) into stats
+        (float64 device tensor of CLOSURE_STATS_DOUBLES, zeroed by the caller)."""
+        if stats.dtype != self.torch.float64 or stats.numel() != CLOSURE_STATS_DOUBLES or not stats.is_contiguous():
+            raise ValueError(f"stats must be a contiguous float64 tensor of {CLOSURE_STATS_DOUBLES}")
+        self._after_torch()
+        _check(lib().qhfpe_closure_stats(self.handle, int(level), _ptr(stats)))
+        self._before_torch()
+
+    def closure_gmfp_kernel(self):
+        """The kernel of Eq. (GMFP) for this handle's bath and grid (numpy float32 [13][13][8][4])."""
+        k = (ctypes.c_float * CLOSURE_KERNEL_FLOATS)()
+        _check(lib().qhfpe_closure_gmfp_kernel(self.handle, k))
+        return np.array(k[:], dtype=np.float32).reshape(13, 13, 8, 4)
+
+    def set_closure(self, kernel=None):
+        """Use the closure kernel (float32 [13][13][8][4] device tensor) at the
+        deepest level; None switches back to Eq. (GMFP)."""
+        t = self.torch
+        if kernel is None:
+            _check(lib().qhfpe_set_closure(self.handle, None, None, 0))
+            self._closure_buf = None
+            return
+        kernel = t.as_tensor(kernel, dtype=t.float32, device=self.device).contiguous()
+        if kernel.numel() != CLOSURE_KERNEL_FLOATS:
+            raise ValueError(f"the closure kernel has {CLOSURE_KERNEL_FLOATS} entries")
+        n = ctypes.c_size_t(0)
+        _check(lib().qhfpe_closure_buffer_bytes(ctypes.byref(self.params), ctypes.byref(n)))
+        self._closure_buf = t.empty(int(n.value), dtype=t.uint8, device=self.device)
+        self._after_torch()
+        _check(lib().qhfpe_set_closure(self.handle, _ptr(kernel), _ptr(self._closure_buf), int(n.value)))
+        self.synchronize()  # the kernel tensor is read during the call
+
+
+def closure_train(stats, iters: int = 3000, lr: float = 3e-3, lr_final: float = 1e-5, seed: int = 1706,
+                  prior=None, ridge: float = 0.0, stream=None):
+    """Train the closure's three layers on the statistics (float64 device
+    tensor), with a ridge pull of weight `ridge` towards the kernel `prior`;
+    returns (composite kernel float32 [13][13][8][4], normalised data loss)."""
+    import torch
+    state = torch.empty(CLOSURE_TRAIN_FLOATS, dtype=torch.float32, device=stats.device)
+    kernel = torch.empty((13, 13, 8, 4), dtype=torch.float32, device=stats.device)
+    if prior is not None:
+        prior = torch.as_tensor(prior, dtype=torch.float32, device=stats.device).contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(stats.device)
+    loss = _c_dbl(0.0)
+    _check(lib().qhfpe_closure_train(_ptr(stats), _ptr(prior) if prior is not None else None, float(ridge),
+                                     _ptr(state), int(seed), int(iters), float(lr), float(lr_final), _ptr(kernel),
+                                     ctypes.byref(loss), ctypes.c_void_p(s.cuda_stream)))
+    return kernel, float(loss.value)
+
+
+def closure_loss(stats, kernel, stream=None) -> float:
+    """The normalised data loss of a closure kernel on the statistics."""
+    import torch
+    kernel = torch.as_tensor(kernel, dtype=torch.float32, device=stats.device).contiguous()
+    state = torch.empty(CLOSURE_TRAIN_FLOATS, dtype=torch.float32, device=stats.device)
+    s = stream if stream is not None else torch.cuda.current_stream(stats.device)
+    loss = _c_dbl(0.0)
+    _check(lib().qhfpe_closure_loss(_ptr(stats), _ptr(kernel), _ptr(state), ctypes.byref(loss),
+                                    ctypes.c_void_p(s.cuda_stream)))
+    return float(loss.value)
 
 
 def stream_copy(dst, src, stream=None):

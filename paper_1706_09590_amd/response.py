@@ -22,7 +22,7 @@ from . import qhfpe
 
 
 def equilibrate(model: dict, tol: float = 1e-10, max_steps: int = 200000, check_every: int = 200,
-                omega: float = 1.0, device=None, dt=None):
+                omega: float = 1.0, device=None, dt=None, closure=None):
     """FP64 real-time relaxation of the full hierarchy from the harmonic
     thermal Wigner function (frequency omega) until ||L W|| / ||W|| < tol.
     dt: the relaxation step (default: the model's).  An RK4 step leaves W
@@ -33,6 +33,8 @@ def equilibrate(model: dict, tol: float = 1e-10, max_steps: int = 200000, check_
     if dt is not None:
         model = dict(model, dt=float(dt))
     P = qhfpe.Propagator(model, batch=1, precision="fp64", device=device)
+    if closure is not None:
+        P.set_closure(closure)
     P.init_thermal(omega)
     steps, res = P.relax(tol, max_steps, check_every)
     W = P.get_state()
@@ -88,7 +90,7 @@ class ThirdOrderProtocol:
     first, so every launch gives the same R3."""
 
     def __init__(self, model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, stride3: int = 1,
-                 precision: str = "fp32", device=None, stream=None):
+                 precision: str = "fp32", device=None, stream=None, closure=None):
         import torch
         self.t1_steps, self.t2_steps = list(t1_steps), list(t2_steps)
         self.n3_steps, self.stride3 = int(n3_steps), int(stride3)
@@ -98,6 +100,10 @@ class ThirdOrderProtocol:
         n1, n2 = len(self.t1_steps), len(self.t2_steps)
         mk = lambda b: qhfpe.Propagator(model, batch=b, precision=precision, device=dev, stream=self.stream)  # noqa: E731
         self.E, self.A, self.B1, self.C = mk(1), mk(1), mk(n1), mk(n1 * n2)
+        if closure is not None:
+            # the learned terminator closes every propagation of the protocol
+            for P in (self.A, self.B1, self.C):
+                P.set_closure(closure)
         W_eq = torch.as_tensor(W_eq, dtype=torch.complex128)
         with torch.cuda.stream(self.stream):
             self.E.set_state(W_eq.to(dev), phase=0)
@@ -187,7 +193,7 @@ class ThirdOrderProtocol:
 
 
 def third_order_response(model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, stride3: int = 1,
-                         precision: str = "fp32", device=None, graph: bool = False):
+                         precision: str = "fp32", device=None, graph: bool = False, closure=None):
     """R3(t3, t2, t1) = (i/hbar)^3 Tr{mu G(t3) mu^x G(t2) mu^x G(t1) mu^x W_eq}.
 
     t1_steps, t2_steps: increasing step counts of the coherence and waiting
@@ -195,7 +201,7 @@ def third_order_response(model: dict, W_eq, t1_steps, t2_steps, n3_steps: int, s
     whole protocol into one graph and launch it (same kernels in the same
     order, so the same result bit for bit).  Returns complex128
     [len(t2_steps)][len(t1_steps)][n3_steps/stride3 + 1]."""
-    pr = ThirdOrderProtocol(model, W_eq, t1_steps, t2_steps, n3_steps, stride3, precision, device)
+    pr = ThirdOrderProtocol(model, W_eq, t1_steps, t2_steps, n3_steps, stride3, precision, device, closure=closure)
     try:
         if graph:
             pr.record()
