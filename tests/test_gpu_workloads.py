@@ -92,6 +92,42 @@ def test_production_size_parity(precision, tile):
         assert err < (tol if precision == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_production_2000_steps_against_the_oracle(precision):
+    """The 256x256 depth-8 workload in the bench's launch configuration (both
+    zetas as one batch, the default stage variant and member groups) over
+    2000 RK4 steps (t = 4) against the stored 2000-step oracle run: the trace
+    at every step and sampled columns of levels 0 and 8 at the end.  FP64:
+    1e-10; FP32 state: 1e-4 on the traces and the absorption spectra."""
+    g = np.load(os.path.join(GOLDEN, "production_2000.npz"))
+    w = inputs.PRODUCTION_ABSORPTION
+    m = w["model"]
+    cols = g["columns"]
+    say(f"production 2000 steps {precision}")
+    P = qhfpe.Propagator(m, batch=len(w["zetas"]), precision=precision)
+    for i, z in enumerate(w["zetas"]):
+        P.set_member_bath(i, z, m["gamma"], m["beta"])
+    P.init_thermal(w["thermal_omega"])
+    P.apply_dipole()
+    tr = P.step(2000, 1)
+    W = P.get_state().cpu().numpy()
+    P.close()
+    trn = tr.cpu().numpy()
+    om = torch.linspace(0.0, 20.0, 2001, dtype=torch.float64)
+    for i, z in enumerate(w["zetas"]):
+        ref = g[f"trace_zeta{z}"]
+        if precision == "fp64":
+            assert rel(trn[i], ref) < 1e-10
+            assert rel(W[i, 0][:, :, cols, :], g[f"level0_zeta{z}"]) < 1e-10
+            scale = np.linalg.norm(g[f"level0_zeta{z}"])
+            assert np.linalg.norm(W[i, -1][:, :, cols, :] - g[f"level_last_zeta{z}"]) / scale < 1e-10
+        else:
+            assert rel(trn[i], ref) < 1e-4
+            I = response.absorption_spectrum((1j / m["hbar"]) * tr[i], m["dt"], om).cpu().numpy()
+            Iref = O.absorption_spectrum((1j / m["hbar"]) * ref, m["dt"], om.numpy())
+            assert spec_err(I, Iref) < 1e-4
+
+
 def test_production_full_length_properties():
     """The full 20000-step production run: finite, R1 exactly real, the first
     100 samples bitwise equal to the 100-step run, and the FP32-state spectra
