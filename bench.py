@@ -208,6 +208,8 @@ def main():
                          "(preparation, t3 propagation)")
     ap.add_argument("--two-d-scale", type=int, default=1,
                     help="divide the 2D spectrum's t1 and t2 counts by this factor (quick runs)")
+    ap.add_argument("--two-d-steps", type=int, default=0,
+                    help="t3 steps of the 2D spectrum (0: the workload's 4000; fewer for profiling runs)")
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
     ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
@@ -356,7 +358,8 @@ def main():
         line["fp32_leg"] = dict(value=leg["value"], unit="cell-updates/s", ms_per_step=leg["ms_per_step"],
                                 roofline=leg["roofline"], spectrum_max_rel_err_vs_fp64=max(errs))
     if not args.no_two_d:
-        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, not args.no_fp64_check_2d, not args.two_d_eager)
+        line["two_d_spectrum"] = two_d_spectrum(args.two_d_scale, not args.no_fp64_check_2d, not args.two_d_eager,
+                                              args.two_d_steps)
     # the optional legs report a failure in the line instead of losing it
     if args.sweep:
         line["uneven_sweep"] = optional_leg(uneven_sweep, args.sweep_steps, args.sweep_streams, args.fp64_check)
@@ -461,7 +464,8 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
                substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
                cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
                finite=bool(all(np.all(np.isfinite(r)) for r in R)),
-               growing_member_ids=info["growing"], growth_flag=sweep.GROWTH_FLAG)
+               growing_member_ids=info["growing"], growth_flag=sweep.GROWTH_FLAG,
+               batch_timings=info["batch_timings"])
     note(f"sweep: FP32 run {t2 - t1:.1f} s")
     if fp64_check:
         from paper_1706_09590_amd import qhfpe
@@ -567,7 +571,7 @@ def paper_case(w: dict, nsteps: int = 0):
     return out
 
 
-def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False):
+def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False, n3_steps: int = 0):
     """Wall time of the batched 2D correlation spectrum: FP64 equilibration of
     the 128x128 depth-6 hierarchy (reported apart), then the t1 / t2
     preparation and all t3 propagations as one batch (FP32 state, FP64
@@ -586,7 +590,7 @@ def two_d_spectrum(scale: int = 1, fp64_check: bool = True, graph: bool = False)
     m = w["model"]
     t1s = w["t1_steps"][:: scale]
     t2s = w["t2_steps"][:: scale]
-    n3, s3 = w["n3_steps"], w["stride3"]
+    n3, s3 = (n3_steps or w["n3_steps"]), w["stride3"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # relaxation at the largest stable RK4 step (the stationary state does not

@@ -39,13 +39,20 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
 // MFMA tile: M = 16 consecutive p, N = 16 = 4 output rows x 4 components,
 // K = 16 taps (dp, ci) of one input row: 13 dp x 8 ci = 104 taps in 7
 // chunks per row, 16 rows.  The weights, already in this B layout
-// [row][chunk][n][k] (closure_weights_kernel), are held in registers.
+// [row][chunk][n][k] (closure_weights_kernel), are held in registers, each
+// wave holding those of half the input rows.
 constexpr int kRowsOut = 4;
 constexpr int kRowsIn = kRowsOut + 2 * kClosureHalf;   // 16
 constexpr int kChunks = 7;
 constexpr int kTaps = (2 * kClosureHalf + 1) * kClosureIn;  // 104 per input row
-constexpr int kApplyWaves = 4;   // one wave per SIMD: each holds all weights (up to 512 registers)
-constexpr int kTilesAtOnce = 2;  // independent accumulators per wave
+// Eight waves: wave w takes the tile pairs w % 4 (+ 4 k) over the input rows
+// (w / 4) * 8 .. + 7, holding those rows' weights in registers; the two
+// halves of each sum meet in LDS.
+constexpr int kApplyWaves = 8;
+constexpr int kRowHalves = 2;
+constexpr int kRowsPerWave = kRowsIn / kRowHalves;  // 8
+constexpr int kTilesAtOnce = 2;  // tiles per wave at once
+constexpr int kChains = 2;       // accumulators per tile (even and odd input rows): 4 independent MFMA chains
 constexpr int kApplyThreads = 64 * kApplyWaves;
 
 // The channels of one grid point as 8 BF16 values (16 bytes).
@@ -76,6 +83,7 @@ __global__ void __launch_bounds__(kApplyThreads, 1)
                          long long comp_stride, int nq, int batch, double p0, double dp,
                          const unsigned short* __restrict__ wb, T* __restrict__ out, long long out_stride) {
   __shared__ __align__(16) unsigned short sx[kRowsIn * NP * kClosureIn];
+  __shared__ f32x4_t sred[kApplyWaves / kRowHalves][kTilesAtOnce][64];  // second-half partial sums
   constexpr int kNewPer = kRowsOut * NP / kApplyThreads;  // new-row points per thread (1 or 2)
   static_assert(kRowsOut * NP % kApplyThreads == 0, "new rows split evenly over the threads");
   const int tid = threadIdx.x;
@@ -86,14 +94,17 @@ __global__ void __launch_bounds__(kApplyThreads, 1)
   const long long t_end = t_begin + per < ntasks ? t_begin + per : ntasks;
   const int lane = tid & 63, wid = tid >> 6;
   const int quad = lane >> 4, li = lane & 15;
-  // every B fragment of the weights stays in this lane's registers: they are
-  // the same for every tile and task
-  bf16x4_t bw[kRowsIn][kChunks];
+  // the B fragments of this wave's input rows stay in its registers: they
+  // are the same for every tile and task
+  const int tg = wid % (kApplyWaves / kRowHalves), half = wid / (kApplyWaves / kRowHalves);
+  bf16x4_t bw[kRowsPerWave][kChunks];
 #pragma unroll
-  for (int row = 0; row < kRowsIn; ++row)
+  for (int rr = 0; rr < kRowsPerWave; ++rr)
 #pragma unroll
-    for (int ch = 0; ch < kChunks; ++ch)
-      bw[row][ch] = *reinterpret_cast<const bf16x4_t*>(wb + (((row * kChunks + ch) * 16 + li) * 16 + 4 * quad));
+    for (int ch = 0; ch < kChunks; ++ch) {
+      const int row = half * kRowsPerWave + rr;
+      bw[rr][ch] = *reinterpret_cast<const bf16x4_t*>(wb + (((row * kChunks + ch) * 16 + li) * 16 + 4 * quad));
+    }
   auto load_point = [&](const T* vb, int q, int a, float c[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = 0.f;
@@ -140,12 +151,16 @@ __global__ void __launch_bounds__(kApplyThreads, 1)
         load_point(vb, q0 + kRowsOut + kClosureHalf + r, a, nxt[j]);
       }
     }
-    for (int t0 = wid * kTilesAtOnce; t0 < NP / 16; t0 += kApplyWaves * kTilesAtOnce) {
-      f32x4_t acc[kTilesAtOnce];
+    constexpr int kGroups = kApplyWaves / kRowHalves;
+    for (int t0 = tg * kTilesAtOnce; t0 < NP / 16; t0 += kGroups * kTilesAtOnce) {
+      f32x4_t acc[kTilesAtOnce][kChains];
 #pragma unroll
-      for (int u = 0; u < kTilesAtOnce; ++u) acc[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int u = 0; u < kTilesAtOnce; ++u)
 #pragma unroll
-      for (int row = 0; row < kRowsIn; ++row) {
+        for (int c = 0; c < kChains; ++c) acc[u][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int row = half * kRowsPerWave + rr;
         const unsigned short* xr = sx + slot(q0 - kClosureHalf + row) * NP * kClosureIn;
 #pragma unroll
         for (int ch = 0; ch < kChunks; ++ch) {
@@ -160,21 +175,32 @@ __global__ void __launch_bounds__(kApplyThreads, 1)
               av = *reinterpret_cast<const bf16x4_t*>(xr + pin * kClosureIn + ci0);
             }
             // B (registers): taps k = 4 quad .. 4 quad + 3 of output n = li
-            acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw[row][ch], acc[u], 0, 0, 0);
+            acc[u][rr % kChains] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw[rr][ch], acc[u][rr % kChains], 0, 0, 0);
           }
         }
       }
-      // D: lane holds rows i = 4 quad .. 4 quad + 3 (p) of column n = li
-      const int r = li >> 2, co = li & 3;
-      const int q = q0 + r;
-      if (q < nq) {
+      // the second row half hands its partial sums to the first
+      if (half == 1) {
 #pragma unroll
-        for (int u = 0; u < kTilesAtOnce; ++u) {
-          T* o = out + (long long)b * out_stride + co * comp_stride + (long long)q * NP + 16 * (t0 + u) + 4 * quad;
+        for (int u = 0; u < kTilesAtOnce; ++u) sred[tg][u][lane] = acc[u][0] + acc[u][1];
+      }
+      __syncthreads();
+      if (half == 0) {
+        // D: lane holds rows i = 4 quad .. 4 quad + 3 (p) of column n = li
+        const int r = li >> 2, co = li & 3;
+        const int q = q0 + r;
+        if (q < nq) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) o[j] = (T)acc[u][j];
+          for (int u = 0; u < kTilesAtOnce; ++u) {
+            const f32x4_t sum = acc[u][0] + acc[u][1] + sred[tg][u][lane];
+            T* o = out + (long long)b * out_stride + co * comp_stride + (long long)q * NP + 16 * (t0 + u) + 4 * quad;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = (T)sum[j];
+          }
         }
       }
+      __syncthreads();  // sred is free again
     }
   }
 }

@@ -33,6 +33,7 @@ library.
 from __future__ import annotations
 
 import threading
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -134,8 +135,11 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
     lock = threading.Lock()
     counts = {"cell_updates": 0}
 
+    timings = []
+
     def run_batch(job):
         mod, ids, subs = job
+        t_start = time.perf_counter()
         s = torch.cuda.Stream(device=dev)
         with torch.cuda.stream(s):
             P = qhfpe.Propagator(inputs.model_dict(mod, dt=dt / subs), batch=len(ids), precision=precision,
@@ -163,6 +167,9 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 results[i] = R1[j]
                 growth[i] = n_end[j] / max(n_mid[j], 1e-300)
             counts["cell_updates"] += cells * len(ids) * nsteps * subs
+            timings.append(dict(grid=mod["nq"], depth=mod["depth"], n_states=mod["n_states"], members=len(ids),
+                                substeps=subs, seconds=time.perf_counter() - t_start,
+                                cell_updates=cells * len(ids) * nsteps * subs))
         return len(ids)
 
     # largest batches first, so that the small ones fill in at the end
@@ -170,7 +177,7 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
     with ThreadPoolExecutor(max_workers=max(1, int(streams))) as ex:
         list(ex.map(run_batch, order))
     info = dict(batches=len(batches), cell_updates=counts["cell_updates"], growth=growth,
-                growing=[int(i) for i in np.flatnonzero(growth > GROWTH_FLAG)])
+                growing=[int(i) for i in np.flatnonzero(growth > GROWTH_FLAG)], batch_timings=timings)
     return results, info
 
 
