@@ -7,7 +7,7 @@ propagations of a depth-10 hierarchy, whose levels 3 and 4 along the way are
 the training pairs of a depth-3 closure.  The statistics of those pairs are
 accumulated on the GPU as the runs go (no pair is stored), the three layers
 are trained by the library's gradient-descent kernels, and the closure is
-judged on the 2D spectra against the plain depth-10 hierarchy.
+compared on the 2D spectra with the plain depth-10 hierarchy.
 
 This module only sequences library calls; all arithmetic runs in the HIP
 library.
