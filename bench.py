@@ -216,7 +216,9 @@ def main():
     ap.add_argument("--closure", action="store_true",
                     help="also train the learned terminator on depth-10 runs of the 2D protocol and compare the "
                          "depth-3 + closure 2D spectra with plain depth 3 and plain depth 10")
-    ap.add_argument("--sweep-streams", type=int, default=1, help="batches of the sweep run concurrently")
+    ap.add_argument("--sweep-streams", type=int, default=1, help="large batches of the sweep run concurrently")
+    ap.add_argument("--sweep-small-streams", type=int, default=-1,
+                    help="small batches of the sweep run this many at a time after the large ones (-1: the default)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the uneven batched sweep (256 members, grids 96^2..256^2, depths 4..10, "
                          "a quarter three-state, 5000 steps, FP32 state)")
@@ -362,7 +364,8 @@ def main():
                                               args.two_d_steps)
     # the optional legs report a failure in the line instead of losing it
     if args.sweep:
-        line["uneven_sweep"] = optional_leg(uneven_sweep, args.sweep_steps, args.sweep_streams, args.fp64_check)
+        line["uneven_sweep"] = optional_leg(uneven_sweep, args.sweep_steps, args.sweep_streams, args.fp64_check,
+                                            args.sweep_small_streams)
     if args.paper:
         line["paper_workload"] = optional_leg(paper_workload, args.paper_steps)
     if args.closure:
@@ -438,12 +441,14 @@ def optional_leg(fn, *a):
         return dict(error=f"{type(e).__name__}: {e}")
 
 
-def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
+def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False, small_streams: int = -1):
     """Wall time of the uneven batched sweep: plan (spectral radius and
     substeps per member, reported apart), then all members as batches of
-    like-shaped members on concurrent streams (`streams` at a time), FP32 state,
-    R1 every step.  fp64_check: run the sweep again with the FP64 state
-    (untimed) and report the largest error of the FP32 absorption spectra."""
+    like-shaped members: the large batches `streams` at a time, then the
+    small ones `small_streams` at a time (sweep.SMALL_STREAMS if negative),
+    FP32 state, R1 every step.  fp64_check: run the sweep again with the FP64
+    state (untimed) and report the largest error of the FP32 absorption
+    spectra."""
     import numpy as np
     import torch
 
@@ -451,16 +456,19 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
     w = inputs.UNEVEN_SWEEP
     nsteps = nsteps or w["nsteps"]
     members = inputs.uneven_sweep_members(w["n_members"], w["seed"])
+    if small_streams < 0:
+        small_streams = sweep.SMALL_STREAMS
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     subs, batches = sweep.plan(members, w["dt"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=streams, batches=batches)
+    R, info = sweep.run_sweep(members, nsteps, w["dt"], precision="fp32", streams=streams, batches=batches,
+                              small_streams=small_streams)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     out = dict(wall_s=t2 - t1, plan_s=t1 - t0, members=len(members), batches=len(batches), rk4_steps=nsteps,
-               batch_streams=streams,
+               batch_streams=streams, small_batch_streams=small_streams, small_batch_reals=sweep.SMALL_REALS,
                substeps_histogram={str(k): int(v) for k, v in zip(*np.unique(subs, return_counts=True))},
                cell_updates=info["cell_updates"], cell_updates_per_s=info["cell_updates"] / (t2 - t1),
                finite=bool(all(np.all(np.isfinite(r)) for r in R)),
@@ -469,7 +477,8 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False):
     note(f"sweep: FP32 run {t2 - t1:.1f} s")
     if fp64_check:
         from paper_1706_09590_amd import qhfpe
-        R64, _ = sweep.run_sweep(members, nsteps, w["dt"], precision="fp64", streams=streams, batches=batches)
+        R64, _ = sweep.run_sweep(members, nsteps, w["dt"], precision="fp64", streams=streams, batches=batches,
+                                 small_streams=small_streams)
         om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
         errs = []
         for r32, r64 in zip(R, R64):

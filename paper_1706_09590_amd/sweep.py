@@ -5,10 +5,13 @@ The linear-absorption protocol of Sec. III (thermal state, impulsive mu^x,
 R1(t) = (i/hbar) Tr{mu W^(0)(t)}, Eq. (R1)) is run for every member.
 Members that share a grid, a depth, a state count and a number of RK4
 substeps form one batch (one library handle, one launch per stage and
-member group, with the stage variant picked by qhfpe_autotune).  The batches
-run one after another by default: a tuned batch fills the GPU, and running
+member group, with the stage variant picked by qhfpe_autotune).  The large
+batches run one after another: a tuned batch fills the GPU, and running
 several at once (each on its own stream from its own host thread; the
-library calls release the interpreter lock) was slower.
+library calls release the interpreter lock) was slower.  The small batches
+(a few members of small grids or shallow hierarchies, and the members split
+off by their substeps) leave most of the GPU idle, their launches bound by
+the latency of one task; they run afterwards, several at a time.
 
 RK4 is only stable for dt |lambda| below about 2.8; members with strong,
 hot baths need substeps.  Each member's spectral radius is estimated by
@@ -42,6 +45,8 @@ from . import inputs, qhfpe
 
 RK4_MARGIN = 2.0  # dt * rho allowed per substep (RK4 is stable to about 2.8)
 GROWTH_FLAG = 2.0  # ||W(T)|| / ||W(T/2)|| above this marks a growing member
+SMALL_REALS = 8_000_000  # batches below this many packed reals leave most of the GPU idle
+SMALL_STREAMS = 8  # small batches run this many at a time
 
 
 def member_model(member: dict, dt: float) -> dict:
@@ -117,14 +122,28 @@ def plan(members, dt: float, estimate_iters: int = 40, device=None):
     return subs, batches
 
 
+def batch_reals(batch) -> int:
+    """Packed reals of a batch's state (all members and levels)."""
+    mod, ids, _ = batch
+    return (mod["depth"] + 1) * mod["nq"] * mod["np"] * mod["n_states"] ** 2 * len(ids)
+
+
 def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams: int = 1, batches=None,
-              thermal_omega: float = 1.0, device=None):
+              thermal_omega: float = 1.0, device=None, small_streams: int = SMALL_STREAMS,
+              small_reals: int = SMALL_REALS):
     """R1(t) for every member, sampled every dt for nsteps steps.
 
     batches: from plan() (computed here if None).  Returns (list of complex128
     numpy arrays [nsteps+1] in member order, info dict).  info["growth"][i]
     is ||W(T)|| / ||W(T/2)|| of member i's own state (T = nsteps dt), and
-    info["growing"] the ids of the members whose growth exceeds GROWTH_FLAG."""
+    info["growing"] the ids of the members whose growth exceeds GROWTH_FLAG.
+
+    small_streams > 0: batches whose state holds fewer than small_reals packed
+    reals are too small to fill the GPU (their stage launches are bound by
+    the latency of one task); they run after the large ones, small_streams
+    of them at a time, each on its own stream (0: every batch in the one
+    sequence).  Concurrent batches may be tuned to another stage variant
+    than alone, which changes the FP32 results at rounding level."""
     import torch
     qhfpe.lib()  # load the library before the worker threads start
     if batches is None:
@@ -148,7 +167,12 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 for j, i in enumerate(ids):
                     m = members[i]
                     P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
+                t_made = time.perf_counter()
                 P.autotune(5)  # the fastest stage variant for this batch's shape and size
+                t_tuned = time.perf_counter()
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(s)
                 P.init_thermal(thermal_omega)
                 P.apply_dipole()
                 # two halves, with the state's norm at the midpoint and the end
@@ -157,6 +181,7 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 n_mid = P.residual()[:, 1]
                 tr_b = P.step((nsteps - half) * subs, subs)
                 n_end = P.residual()[:, 1]
+                ev1.record(s)
                 tr = torch.cat([tr_a, tr_b[:, 1:]], dim=1)
                 R1 = ((1j / mod.get("hbar", 1.0)) * tr).cpu().numpy()
             finally:
@@ -169,13 +194,23 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
             counts["cell_updates"] += cells * len(ids) * nsteps * subs
             timings.append(dict(grid=mod["nq"], depth=mod["depth"], n_states=mod["n_states"], members=len(ids),
                                 substeps=subs, seconds=time.perf_counter() - t_start,
+                                setup_s=t_made - t_start, tune_s=t_tuned - t_made,
+                                gpu_s=ev0.elapsed_time(ev1) * 1e-3,
                                 cell_updates=cells * len(ids) * nsteps * subs))
         return len(ids)
 
     # largest batches first, so that the small ones fill in at the end
     order = sorted(batches, key=lambda b: -(b[0]["depth"] + 1) * b[0]["nq"] * b[0]["np"] * len(b[1]) * b[2])
+    if small_streams > 0:
+        large = [b for b in order if batch_reals(b) >= small_reals]
+        small = [b for b in order if batch_reals(b) < small_reals]
+    else:
+        large, small = order, []
     with ThreadPoolExecutor(max_workers=max(1, int(streams))) as ex:
-        list(ex.map(run_batch, order))
+        list(ex.map(run_batch, large))
+    if small:
+        with ThreadPoolExecutor(max_workers=int(small_streams)) as ex:
+            list(ex.map(run_batch, small))
     info = dict(batches=len(batches), cell_updates=counts["cell_updates"], growth=growth,
                 growing=[int(i) for i in np.flatnonzero(growth > GROWTH_FLAG)], batch_timings=timings)
     return results, info
@@ -218,5 +253,5 @@ def sweep_cell_updates(members, nsteps: int, substeps) -> int:
     return int(sum((m["depth"] + 1) * m["grid"] ** 2 * nsteps * int(s) for m, s in zip(members, substeps)))
 
 
-__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "run_sweep", "amplification",
-           "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG"]
+__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "batch_reals", "run_sweep", "amplification",
+           "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG", "SMALL_REALS", "SMALL_STREAMS"]

@@ -41,3 +41,15 @@ def test_member_model_shapes():
         assert mod["depth"] == m[i]["depth"] and mod["n_states"] == m[i]["n_states"]
         assert len(mod["poly"]) == mod["n_states"] and len(mod["mu"]) == mod["n_states"]
         assert mod["zeta"] == m[i]["zeta"] and mod["beta"] == m[i]["beta"]
+
+
+def test_batch_size_rule():
+    # packed reals of a batch: levels x cells x n_s^2 x members
+    mod = sweep.member_model(dict(grid=256, depth=8, n_states=2, zeta=1.0, gamma=1.0, beta=1.0), 0.002)
+    assert sweep.batch_reals((mod, [0, 1], 1)) == 9 * 256 * 256 * 4 * 2
+    mod3 = sweep.member_model(dict(grid=96, depth=4, n_states=3, zeta=1.0, gamma=1.0, beta=1.0), 0.002)
+    assert sweep.batch_reals((mod3, [0, 1, 2, 3], 2)) == 5 * 96 * 96 * 9 * 4
+    # the production-size single member is small, a full 256^2 depth-10 batch of 12 is not
+    assert sweep.batch_reals((mod, [0], 3)) < sweep.SMALL_REALS
+    big = sweep.member_model(dict(grid=256, depth=10, n_states=2, zeta=1.0, gamma=1.0, beta=1.0), 0.002)
+    assert sweep.batch_reals((big, list(range(12)), 1)) >= sweep.SMALL_REALS
