@@ -136,8 +136,21 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
                               has_y ? level_bytes : 0u);
   const unsigned cbytes = cs * ES;   // soffset step per packed component
 
-  for (int j = tid; j < N1 * (N2 + 1); j += NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
-  for (int j = tid; j < 2 * NP; j += NT) ssym[j] = static_cast<const T*>(a.psym)[j];
+  // the twiddle and symbol tables are loaded first and stored to LDS just
+  // before the first barrier, so that their latency overlaps phase P1 (the
+  // loads complete in issue order: by then P1 has waited for later ones).
+  // Lanes past a table's end load its last entry and store nothing.
+  constexpr int NTW = N1 * (N2 + 1), NSY = 2 * NP;
+  constexpr int RTW = (NTW + NT - 1) / NT, RSY = (NSY + NT - 1) / NT;
+  T twr[RTW][2], syr[RSY];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) {
+    const T* const t = static_cast<const T*>(a.twiddle2) + 2 * min(tid + r * NT, NTW - 1);
+    twr[r][0] = t[0];
+    twr[r][1] = t[1];
+  }
+#pragma unroll
+  for (int r = 0; r < RSY; ++r) syr[r] = static_cast<const T*>(a.psym)[min(tid + r * NT, NSY - 1)];
 
   const T p = T(a.p0 + ia * a.dp);
   const double* bath = a.bath + kBathStride * b;
@@ -242,6 +255,16 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   for (int i = 0; i < CPT; ++i)
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) base[i][comp] = buf_load<T>(ry, qo[i + 3], comp * cbytes);
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) {
+    const int j = tid + r * NT;
+    if (j < NTW) stw[j] = cx<T>{twr[r][0], twr[r][1]};
+  }
+#pragma unroll
+  for (int r = 0; r < RSY; ++r) {
+    const int j = tid + r * NT;
+    if (j < NSY) ssym[j] = syr[r];
+  }
   __syncthreads();
 
   // ---- P2: D_p of the level-coupling field -------------------------------

@@ -78,8 +78,10 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
 
 // QC: q-dependent diabatic coupling U_01(q), applied in the r-space multiply
 // (it mixes the packed-diagonal and coherence transforms of a column).
+// Occupancy: FP32 without QC is held to four waves per SIMD (128 VGPRs); the
+// others run two (FP64: 79 KB of LDS per workgroup allows no more).
 template <typename T, int NP, bool QC>
-__global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageArgs a) {
+__global__ void __launch_bounds__(WavePlan<NP>::NT, sizeof(T) == 4 && !QC ? 4 : 2) stage_wave_kernel(StageArgs a) {
   using W = WavePlan<NP>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
   constexpr int I1 = W::I1, I2 = W::I2;
@@ -90,10 +92,6 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   __shared__ T ssym[2 * NP];             // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
 
   const int tid = threadIdx.x;
-  for (int j = tid; j < N1 * (N2 + 1); j += W::NT) stw[j] = static_cast<const cx<T>*>(a.twiddle2)[j];
-  for (int j = tid; j < 2 * NP; j += W::NT) ssym[j] = static_cast<const T*>(a.psym)[j];
-  __syncthreads();  // the only workgroup barrier
-
   // the wave index is uniform across the wave; saying so keeps every
   // quantity derived from it (task, level, member, buffer descriptors) in
   // scalar registers instead of per-lane loops over descriptor values
@@ -104,8 +102,11 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   const int ntasks = ntiles * L * a.batch;
   // levels fastest, as in stage_kernel: the tasks of all levels of one
   // column group run together and share their level neighbours through L2
-  const int task = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
-  if (task >= ntasks) return;
+  const int task_id = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
+  // a wave past the last task still meets its workgroup at the table
+  // barrier below; it takes task 0's indices and ends after the barrier
+  const bool active = task_id < ntasks;
+  const int task = active ? task_id : 0;
   const int n = task % L;
   const int tile = (task / L) % ntiles;
   const int b = task / (L * ntiles);
@@ -175,12 +176,14 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
 
   // ---- local terms, one component at a time ------------------------------
   // v^(n) at the task columns is the middle of the kinetic window, so it is
-  // loaded once.  In FP32 the loads of component c + 1 are issued while
-  // component c is computed, into second register slots: the window and y
-  // after c's kinetic term, v^(n +- 1) after c's level terms.  Double has no
-  // registers for a second window; it issues all loads of component c + 1
-  // once component c is done.
-  constexpr bool kPipe = sizeof(T) == 4;
+  // loaded once.  In FP32 at np = 128 the loads of component c + 1 are
+  // issued while component c is computed, into second register slots: the
+  // window and y after c's kinetic term, v^(n +- 1) after c's level terms.
+  // Double has no registers for a second window; it issues all loads of
+  // component c + 1 once component c is done.  FP32 at np = 256 does the
+  // same as double: without the second slots it holds four waves per SIMD
+  // instead of three, which is faster there.
+  constexpr bool kPipe = sizeof(T) == 4 && NP == 128;
   constexpr int NSW = kPipe ? 2 : 1;  // window slots
   T base[C][NC][K];  // y + coef * (all terms except the potential)
   T lw[2][2][C][K];     // v^(n+1), v^(n-1) at the task columns
@@ -210,9 +213,44 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
   // component, reading W00 and W11 back from this lane's own LDS entries
   const bool has_coup = a.coup[0][1] != 0.0;
   const T dcoef = T(a.coef * a.coup[0][1]);
-  issue_window(0, 0);
-  issue_y(0, 0);
-  issue_level(0, 0);
+  // The twiddle and symbol tables go to LDS behind the workgroup's only
+  // barrier.  Their loads are issued first and the first component's loads
+  // right after them, so that the wait for the tables (loads complete in
+  // issue order) does not wait for the component and the component's
+  // latency overlaps the table stores and the barrier.
+  {
+    constexpr int NTW = N1 * (N2 + 1), NSY = 2 * NP;
+    constexpr int RTW = (NTW + W::NT - 1) / W::NT, RSY = (NSY + W::NT - 1) / W::NT;
+    T twr[RTW][2], syr[RSY];  // (plain scalars: an array of cx<T> went to scratch)
+    // (lanes past a table's end load its last entry and store nothing, so
+    // that the loads need no branch)
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+      const T* const t = static_cast<const T*>(a.twiddle2) + 2 * min(tid + r * W::NT, NTW - 1);
+      twr[r][0] = t[0];
+      twr[r][1] = t[1];
+    }
+#pragma unroll
+    for (int r = 0; r < RSY; ++r) syr[r] = static_cast<const T*>(a.psym)[min(tid + r * W::NT, NSY - 1)];
+    __builtin_amdgcn_sched_barrier(0);
+    // (an inactive wave loads task 0's data too: in bounds, and no branch)
+    issue_window(0, 0);
+    issue_y(0, 0);
+    issue_level(0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+      const int j = tid + r * W::NT;
+      if (j < NTW) stw[j] = cx<T>{twr[r][0], twr[r][1]};
+    }
+#pragma unroll
+    for (int r = 0; r < RSY; ++r) {
+      const int j = tid + r * W::NT;
+      if (j < NSY) ssym[j] = syr[r];
+    }
+    __syncthreads();  // the only workgroup barrier
+  }
+  if (!active) return;
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     const int ws = kPipe ? (comp & 1) : 0;
@@ -353,21 +391,28 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
       }
     }
   }
-  // q-dependent coupling: U_01(q + r/2), U_01(q - r/2) of this lane's rows
-  T cP[QC ? I2 : 1][QC ? N2 : 1], cM[QC ? I2 : 1][QC ? N2 : 1];
-  if constexpr (QC) {
-    const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
-    const rsrc_t rt = make_rsrc(a.mtab, (unsigned)kWaveTables * tbytes);
+  // q-dependent coupling: U_01(q + r/2), U_01(q - r/2) of this lane's rows.
+  // In FP32 they are loaded here with the other multipliers; in FP64 they
+  // are loaded four at a time inside the r-space loop, since holding all of
+  // them through the forward passes would exceed the register budget.
+  constexpr bool kQcEarly = QC && sizeof(T) == 4;
+  const unsigned qc_tbytes = (unsigned)((long long)nq * NP * ES);
+  const rsrc_t qc_rt = make_rsrc(a.mtab, (unsigned)kWaveTables * qc_tbytes);
+  auto qc_row = [&](int t) {
+    const int item = lane + 64 * t;
+    const int f = item / N1, k1 = item % N1;
+    const int qc = min(q0 + f % C, nq - 1);
+    return ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
+  };
+  T cP[kQcEarly ? I2 : 1][kQcEarly ? N2 : 1], cM[kQcEarly ? I2 : 1][kQcEarly ? N2 : 1];
+  if constexpr (kQcEarly) {
 #pragma unroll
     for (int t = 0; t < I2; ++t) {
-      const int item = lane + 64 * t;
-      const int f = item / N1, k1 = item % N1;
-      const int qc = min(q0 + f % C, nq - 1);
-      const unsigned row = ((unsigned)qc * NP + (unsigned)k1 * N2) * ES;
+      const unsigned row = qc_row(t);
 #pragma unroll
       for (int k2 = 0; k2 < N2; k2 += 4) {
-        const Quad<T> qp = buf_load4(rt, 3u * tbytes + row + k2 * ES, 0, T(0));
-        const Quad<T> qm = buf_load4(rt, 4u * tbytes + row + k2 * ES, 0, T(0));
+        const Quad<T> qp = buf_load4(qc_rt, 3u * qc_tbytes + row + k2 * ES, 0, T(0));
+        const Quad<T> qm = buf_load4(qc_rt, 4u * qc_tbytes + row + k2 * ES, 0, T(0));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           cP[t][k2 + j] = qp.v[j];
@@ -425,8 +470,16 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
     const T* const opr = ore + pbase;
     const T* const opi = ore + LDP + pbase;
     const T hk = kind ? T(0.5) : T(1);
+    Quad<T> qp4{}, qm4{};  // FP64: the coupling values of k2 .. k2 + 3
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
+      if constexpr (QC && !kQcEarly) {
+        if (k2 % 4 == 0) {
+          __builtin_amdgcn_sched_barrier(0);
+          qp4 = buf_load4(qc_rt, 3u * qc_tbytes + qc_row(t) + k2 * ES, 0, T(0));
+          qm4 = buf_load4(qc_rt, 4u * qc_tbytes + qc_row(t) + k2 * ES, 0, T(0));
+        }
+      }
       const cx<T> z = {zr[k2], zi[k2]};
       const cx<T> zp = {pr[-k2], -pi[-k2]};
       const T e = cdel * ssym[k1 + N1 * k2] + c0t * ssym[NP + k1 + N1 * k2];
@@ -441,7 +494,15 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, 2) stage_wave_kernel(StageAr
         //   coherence        += (-c+ + i c-)/2 Z + (c+ + i c-)/2 Z'     (Z = packed diagonals)
         const cx<T> zo = {ozr[k2], ozi[k2]};
         const cx<T> zop = {opr[-k2], -opi[-k2]};
-        const T xp = hk * cP[t][k2], xm = hk * cM[t][k2];
+        T cp, cm;
+        if constexpr (kQcEarly) {
+          cp = cP[t][k2];
+          cm = cM[t][k2];
+        } else {
+          cp = qp4.v[k2 % 4];
+          cm = qm4.v[k2 % 4];
+        }
+        const T xp = hk * cp, xm = hk * cm;
         const cx<T> al = {kind ? -xp : xp, xm};
         const cx<T> be = {kind ? xp : -xm, kind ? xm : -xp};
         yk[t][k2].re += al.re * zo.re - al.im * zo.im + be.re * zop.re - be.im * zop.im;
