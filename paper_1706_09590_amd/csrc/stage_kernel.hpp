@@ -188,8 +188,10 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   // components are processed in groups of LGRP; the scheduling barrier keeps
   // the next group's loads from being hoisted, which bounds register use.
   // FP64 tiles are held to two workgroups per CU by LDS, which leaves room
-  // for all loads at once; FP32 runs four workgroups and loads in halves.
-  constexpr int LGRP = (sizeof(T) == 8) ? NC : 2;
+  // for all loads at once, and so are three-state FP32 tiles (three per CU;
+  // all loads at once measured 2% faster there); two-state FP32 runs four
+  // workgroups and loads in halves.
+  constexpr int LGRP = (sizeof(T) == 8 || NS == 3) ? NC : 2;
 #pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     if (comp % LGRP == 0 && comp > 0) __builtin_amdgcn_sched_barrier(0);
