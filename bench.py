@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--closure", action="store_true",
                     help="also train the learned terminator on depth-10 runs of the 2D protocol and compare the "
                          "depth-3 + closure 2D spectra with plain depth 3 and plain depth 10")
+    ap.add_argument("--closure-depths", default="",
+                    help="comma-separated closed depths: the learned terminator at each depth N (trained on the "
+                         "levels N, N + 1 of the same depth-10 runs) against plain depth N, both against depth 10")
     ap.add_argument("--sweep-streams", type=int, default=1, help="large batches of the sweep run concurrently")
     ap.add_argument("--sweep-small-streams", type=int, default=-1,
                     help="small batches of the sweep run this many at a time after the large ones (-1: the default)")
@@ -370,6 +373,8 @@ def main():
         line["paper_workload"] = optional_leg(paper_workload, args.paper_steps)
     if args.closure:
         line["learned_closure"] = optional_leg(learned_closure)
+    if args.closure_depths:
+        line["closure_depth_scan"] = optional_leg(closure_depth_scan, [int(x) for x in args.closure_depths.split(",")])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline([inputs.model_dict(base, zeta=z) for z in zetas])
         note("cpu baseline done")
@@ -422,6 +427,41 @@ def learned_closure():
                speedup_vs_fp64_single_trajectory=one * B / wc, speedup_vs_plain10_batched=w10 / wc)
     note("closure comparison done")
     del np
+    return out
+
+
+def closure_depth_scan(depths):
+    """The 2D spectrum (64 x 16 x 4000, FP32 state, recorded graphs) at each
+    closed depth N, plain and with a learned terminator trained on the level
+    pairs (N, N + 1) of one set of depth-10 runs (as in learned_closure),
+    with the spectral errors against plain depth 10 and the wall times."""
+    import torch
+
+    from paper_1706_09590_amd import closure, inputs, response
+    w = inputs.TWO_D_SPECTRUM
+    m = w["model"]
+    m10 = inputs.model_dict(m, depth=10)
+    t1s, t2s, n3 = w["t1_steps"], w["t2_steps"], w["n3_steps"]
+    om = torch.linspace(0.0, 20.0, 401, dtype=torch.float64, device="cuda")
+    W10, _, _ = response.equilibrate(m10, tol=1e-10, max_steps=200000, check_every=500, dt=response.relax_step(m10))
+    stats, planes = closure.training_statistics(m10, W10, t1s[::2], t2s, n3, 250, list(depths))
+    note("closure depth scan: statistics done")
+
+    def err(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+    I10c, I10t, w10, _ = closure.two_d_spectra(m10, t1s, t2s, n3, om)
+    out = dict(training_planes=planes, ridge=closure.RIDGE, plain10_wall_s=w10, depths={})
+    for N in depths:
+        mN = inputs.model_dict(m, depth=N)
+        K, loss = closure.train(stats[N], mN, iters=3000)
+        Ic, It, wp, _ = closure.two_d_spectra(mN, t1s, t2s, n3, om)
+        Kc, Kt, wc, _ = closure.two_d_spectra(mN, t1s, t2s, n3, om, closure=K)
+        out["depths"][str(N)] = dict(
+            train_data_loss=loss, gmfp_data_loss=qhfpe_loss(stats[N], closure.gmfp_kernel(mN)),
+            plain_wall_s=wp, plain_corr_err=err(Ic, I10c), plain_tas_err=err(It, I10t),
+            closure_wall_s=wc, closure_corr_err=err(Kc, I10c), closure_tas_err=err(Kt, I10t),
+            finite=bool(torch.isfinite(Kc).all() and torch.isfinite(Kt).all()))
+        note(f"closure depth scan: depth {N} done")
     return out
 
 

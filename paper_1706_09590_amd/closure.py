@@ -29,13 +29,16 @@ RIDGE = 0.03
 
 
 def training_statistics(model_deep: dict, W_eq, t1_steps, t2_steps, n3_steps: int, sample_every: int,
-                        level: int, precision: str = "fp32", device=None):
+                        level, precision: str = "fp32", device=None):
     """Run the 2D protocol of the deep model (len(t1) x len(t2) t3 runs from
     W_eq) and accumulate the closure statistics of the pairs (level,
     level + 1) of every run every `sample_every` t3 steps.  Returns the
-    float64 statistics tensor and the number of sampled planes."""
+    float64 statistics tensor and the number of sampled planes; with a list
+    of levels, a dict level -> statistics from the same runs."""
+    levels = list(level) if isinstance(level, (list, tuple)) else [level]
     pr = response.ThirdOrderProtocol(model_deep, W_eq, t1_steps, t2_steps, n3_steps, 1, precision, device)
-    stats = torch.zeros(qhfpe.CLOSURE_STATS_DOUBLES, dtype=torch.float64, device=pr.trace.device)
+    stats = {n: torch.zeros(qhfpe.CLOSURE_STATS_DOUBLES, dtype=torch.float64, device=pr.trace.device)
+             for n in levels}
     planes = 0
     try:
         pr.enqueue_prep()
@@ -43,13 +46,14 @@ def training_statistics(model_deep: dict, W_eq, t1_steps, t2_steps, n3_steps: in
         with torch.cuda.stream(pr.stream):
             for _ in range(n3_steps // sample_every):
                 C.step(sample_every, 1, record=False, asynchronous=True)
-                C.closure_stats(level, stats)
+                for n in levels:
+                    C.closure_stats(n, stats[n])
                 planes += C.batch
         for P in (pr.A, pr.B1, pr.C):
             P.status()
     finally:
         pr.close()
-    return stats, planes
+    return (stats if isinstance(level, (list, tuple)) else stats[levels[0]]), planes
 
 
 def gmfp_kernel(model: dict):
