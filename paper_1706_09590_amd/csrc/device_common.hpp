@@ -222,16 +222,20 @@ __device__ __forceinline__ Quad<double> buf_load4(rsrc_t r, unsigned voff, unsig
       __builtin_bit_cast(qhfpe_d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff + 16, (int)soff, 0));
   return {{x[0], x[1], y[0], y[1]}};
 }
+// CPOL: cache policy of the store (0, or kStoreNT for non-temporal stores)
+constexpr int kStoreNT = 2;  // the nt bit of the buffer instructions' cache policy
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_store4(const Quad<float>& q, rsrc_t r, unsigned voff, unsigned soff) {
   using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
   const qhfpe_f4 x = {q.v[0], q.v[1], q.v[2], q.v[3]};
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, CPOL);
 }
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_store4(const Quad<double>& q, rsrc_t r, unsigned voff, unsigned soff) {
   using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
   const qhfpe_d2 x = {q.v[0], q.v[1]}, y = {q.v[2], q.v[3]};
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, y), r, (int)voff + 16, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, CPOL);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, y), r, (int)voff + 16, (int)soff, CPOL);
 }
 
 // M consecutive elements per lane (M * sizeof(T) = 8, 16 or 32 bytes; voff

@@ -412,6 +412,13 @@ struct qhfpe_handle {
     a.ntiles = ntiles();
     a.batch = p.batch;
     a.nblocks_padded = padded_blocks(p.batch);
+    // the three state arrays of the step against the MI355X's 256 MB
+    // memory-side cache: above it, the stage outputs are stored
+    // non-temporally (measured: 1024-member 128x128 depth-6 FP32 launch
+    // 1248 -> 1201 us; at 113 MB, two 256x256 depth-8 FP64 members, the
+    // same stores cost 17%)
+    constexpr double kMemorySideCacheBytes = 256.0 * 1024 * 1024;
+    a.stream_out = 3.0 * (double)L.member_elems * p.batch * L.elem > kMemorySideCacheBytes ? 1 : 0;
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;

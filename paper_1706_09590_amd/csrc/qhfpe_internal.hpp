@@ -82,6 +82,8 @@ struct StageArgs {
   int ntiles;
   int batch;
   int nblocks_padded;       // grid size: ntiles * (depth+1) * batch rounded up to a multiple of 8
+  int stream_out;           // wave variant: 1 = non-temporal output stores (the state exceeds the
+                            // memory-side cache)
   long long member_stride;  // elements per member
   long long level_stride;   // elements per level
   long long comp_stride;    // elements per packed component (nq * np)

@@ -53,26 +53,26 @@ struct WavePlan {
 
 // M consecutive elements per lane stored with one or two 16-byte (or one
 // 8-byte) accesses; voff aligned to the access size.
-template <int M>
+template <int M, int CPOL = 0>
 __device__ __forceinline__ void buf_store_n(const float* v, rsrc_t r, unsigned voff, unsigned soff) {
   if constexpr (M == 2) {
     using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
     const qhfpe_f2 x = {v[0], v[1]};
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, (int)voff, (int)soff, CPOL);
   } else {
     static_assert(M == 4, "2 or 4 floats");
-    buf_store4(Quad<float>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
+    buf_store4<CPOL>(Quad<float>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
   }
 }
-template <int M>
+template <int M, int CPOL = 0>
 __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned voff, unsigned soff) {
   if constexpr (M == 2) {
     using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
     const qhfpe_d2 x = {v[0], v[1]};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, (int)voff, (int)soff, CPOL);
   } else {
     static_assert(M == 4, "2 or 4 doubles");
-    buf_store4(Quad<double>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
+    buf_store4<CPOL>(Quad<double>{{v[0], v[1], v[2], v[3]}}, r, voff, soff);
   }
 }
 
@@ -80,7 +80,9 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
 // (it mixes the packed-diagonal and coherence transforms of a column).
 // Occupancy: FP32 without QC is held to four waves per SIMD (128 VGPRs); the
 // others run two (FP64: 79 KB of LDS per workgroup allows no more).
-template <typename T, int NP, bool QC>
+// NTS: non-temporal output stores (the launcher picks it when the state
+// arrays exceed the memory-side cache, StageArgs::stream_out).
+template <typename T, int NP, bool QC, bool NTS = false>
 __global__ void __launch_bounds__(WavePlan<NP>::NT, sizeof(T) == 4 && !QC ? 4 : 2) stage_wave_kernel(StageArgs a) {
   using W = WavePlan<NP>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
@@ -559,7 +561,11 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, sizeof(T) == 4 && !QC ? 4 : 
     for (int comp = 0; comp < NC; ++comp) {
 #pragma unroll
       for (int j = 0; j < K; ++j) o[comp][j] = base[i][comp][j] + coef * s[(i * NC + comp) * LDP + pad(a0 + j)];
-      buf_store_n<K>(o[comp], ro, qo[i + 3], comp * cbytes);
+      // non-temporal stores (NTS) when the state arrays exceed the
+      // memory-side cache: the output is read back only by the next stage
+      // launch, from HBM anyway, and the stores then drain during the launch
+      // instead of leaving dirty lines for the end-of-launch write-back
+      buf_store_n<K, NTS ? kStoreNT : 0>(o[comp], ro, qo[i + 3], comp * cbytes);
     }
     if (want_trace) {
 #pragma unroll
@@ -577,13 +583,19 @@ template <typename T>
 hipError_t launch_stage_wave(int np, const StageArgs& a, int nblocks, hipStream_t s) {
   switch (np * 2 + (a.qcoup ? 1 : 0)) {
     case 256:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 128, false>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
+      if (a.stream_out)
+        hipLaunchKernelGGL((stage_wave_kernel<T, 128, false, true>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
+      else
+        hipLaunchKernelGGL((stage_wave_kernel<T, 128, false>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
       return hipGetLastError();
     case 257:
       hipLaunchKernelGGL((stage_wave_kernel<T, 128, true>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
       return hipGetLastError();
     case 512:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 256, false>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
+      if (a.stream_out)
+        hipLaunchKernelGGL((stage_wave_kernel<T, 256, false, true>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
+      else
+        hipLaunchKernelGGL((stage_wave_kernel<T, 256, false>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
       return hipGetLastError();
     case 513:
       hipLaunchKernelGGL((stage_wave_kernel<T, 256, true>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
