@@ -412,6 +412,7 @@ struct qhfpe_handle {
     a.ntiles = ntiles();
     a.batch = p.batch;
     a.nblocks_padded = padded_blocks(p.batch);
+    a.wpb = wave_wpb(p.batch);
     // the three state arrays of the step against the MI355X's 256 MB
     // memory-side cache: above it, the stage outputs are stored
     // non-temporally (measured: 1024-member 128x128 depth-6 FP32 launch
@@ -435,10 +436,16 @@ struct qhfpe_handle {
     return a;
   }
 
+  // waves per workgroup of a wave-variant launch over `batch` members
+  int wave_wpb(int batch) const {
+    return (!qcoup && ntiles() * levels * batch <= kWaveSmallTasks) ? kWaveTasksPerBlockSmall : kWaveTasksPerBlock;
+  }
+
   // grid of a stage launch over `batch` members, rounded up to a multiple of 8
   int padded_blocks(int batch) const {
     const int units = ntiles() * levels * batch;  // workgroups, or waves of the wave variant
-    const int blocks = wave() ? (units + kWaveTasksPerBlock - 1) / kWaveTasksPerBlock : units;
+    const int wpb = wave_wpb(batch);
+    const int blocks = wave() ? (units + wpb - 1) / wpb : units;
     return (blocks + 7) / 8 * 8;
   }
 
@@ -453,6 +460,7 @@ struct qhfpe_handle {
     if (a.partials) a.partials += (long long)first * kRespSlots * a.ntiles;
     a.batch = count;
     a.nblocks_padded = padded_blocks(count);
+    a.wpb = wave_wpb(count);
     return a;
   }
 

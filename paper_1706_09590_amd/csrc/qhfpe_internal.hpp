@@ -50,7 +50,13 @@ inline int cpt_default(int /*elem_bytes*/, int ns) { return (ns == 3) ? 2 : 4; }
 constexpr int kTileWave = 1;
 constexpr int kMaxGroups = 4;  // member groups (streams) of qhfpe_step
 constexpr int kWaveTables = 5;  // multiplier planes of the wave variant
-constexpr int kWaveTasksPerBlock = 4;  // waves per workgroup of the wave variant
+// Waves per workgroup of the wave variant: four share the twiddle and symbol
+// tables in LDS; launches of at most kWaveSmallTasks tasks (one round on the
+// GPU) use two, whose finer workgroups spread the waves more evenly over the
+// CUs and so shorten the launch's tail.
+constexpr int kWaveTasksPerBlock = 4;
+constexpr int kWaveTasksPerBlockSmall = 2;
+constexpr int kWaveSmallTasks = 2048;
 inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
 // q columns per task of the wave variant (a lane holds np / 64 p nodes)
 constexpr int wave_columns(int np) { return 512 / np; }
@@ -84,6 +90,8 @@ struct StageArgs {
   int nblocks_padded;       // grid size: ntiles * (depth+1) * batch rounded up to a multiple of 8
   int stream_out;           // wave variant: 1 = non-temporal output stores (the state exceeds the
                             // memory-side cache)
+  int wpb;                  // wave variant: waves (tasks) per workgroup, kWaveTasksPerBlock or
+                            // kWaveTasksPerBlockSmall
   long long member_stride;  // elements per member
   long long level_stride;   // elements per level
   long long comp_stride;    // elements per packed component (nq * np)

@@ -34,7 +34,7 @@
 
 namespace qhfpe {
 
-template <int NP_>
+template <int NP_, int WPB_ = kWaveTasksPerBlock>
 struct WavePlan {
   static constexpr int NP = NP_;
   static constexpr int N1 = FftSplit<NP>::N1, N2 = FftSplit<NP>::N2;
@@ -44,7 +44,7 @@ struct WavePlan {
   static constexpr int NF = 2 * C;             // complex transforms per task
   static constexpr int I1 = NF * N2 / 64;      // items per lane, stride-N2 passes
   static constexpr int I2 = NF * N1 / 64;      // items per lane, contiguous passes
-  static constexpr int WPB = kWaveTasksPerBlock;  // waves per workgroup
+  static constexpr int WPB = WPB_;  // waves per workgroup
   static constexpr int NT = 64 * WPB;
   static constexpr int LDP0 = NP + NP / N2;
   static constexpr int LDP = LDP0 + ((4 - LDP0 % 16) + 16) % 16;
@@ -81,10 +81,12 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
 // Occupancy: FP32 without QC is held to four waves per SIMD (128 VGPRs); the
 // others run two (FP64: 79 KB of LDS per workgroup allows no more).
 // NTS: non-temporal output stores (the launcher picks it when the state
-// arrays exceed the memory-side cache, StageArgs::stream_out).
-template <typename T, int NP, bool QC, bool NTS = false>
-__global__ void __launch_bounds__(WavePlan<NP>::NT, sizeof(T) == 4 && !QC ? 4 : 2) stage_wave_kernel(StageArgs a) {
-  using W = WavePlan<NP>;
+// arrays exceed the memory-side cache, StageArgs::stream_out).  WPB: waves
+// per workgroup (StageArgs::wpb).
+template <typename T, int NP, bool QC, bool NTS = false, int WPB_ = kWaveTasksPerBlock>
+__global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !QC ? 16 : 8) / WPB_)
+    stage_wave_kernel(StageArgs a) {
+  using W = WavePlan<NP, WPB_>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
   constexpr int I1 = W::I1, I2 = W::I2;
   constexpr int LDP = W::LDP;
@@ -579,29 +581,38 @@ __global__ void __launch_bounds__(WavePlan<NP>::NT, sizeof(T) == 4 && !QC ? 4 : 
   }
 }
 
+template <typename T, int NP, bool QC, bool NTS, int WPB>
+hipError_t launch_wave_one(const StageArgs& a, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((stage_wave_kernel<T, NP, QC, NTS, WPB>), dim3(nblocks), dim3(WavePlan<NP, WPB>::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+// instantiations: plain stores in both workgroup sizes and non-temporal
+// stores (large states, so large launches) with four waves per workgroup for
+// a constant coupling; four waves per workgroup for a q-dependent one (two
+// would make the compiler trade registers for a higher occupancy and spill)
+template <typename T, int NP, bool QC>
+hipError_t launch_wave_np(const StageArgs& a, int nblocks, hipStream_t s) {
+  if constexpr (!QC) {
+    if (a.wpb == kWaveTasksPerBlockSmall)
+      return launch_wave_one<T, NP, false, false, kWaveTasksPerBlockSmall>(a, nblocks, s);
+    if (a.wpb != kWaveTasksPerBlock) return hipErrorInvalidValue;
+    if (a.stream_out) return launch_wave_one<T, NP, false, true, kWaveTasksPerBlock>(a, nblocks, s);
+    return launch_wave_one<T, NP, false, false, kWaveTasksPerBlock>(a, nblocks, s);
+  } else {
+    if (a.wpb != kWaveTasksPerBlock) return hipErrorInvalidValue;
+    return launch_wave_one<T, NP, true, false, kWaveTasksPerBlock>(a, nblocks, s);
+  }
+}
+
 template <typename T>
 hipError_t launch_stage_wave(int np, const StageArgs& a, int nblocks, hipStream_t s) {
   switch (np * 2 + (a.qcoup ? 1 : 0)) {
-    case 256:
-      if (a.stream_out)
-        hipLaunchKernelGGL((stage_wave_kernel<T, 128, false, true>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
-      else
-        hipLaunchKernelGGL((stage_wave_kernel<T, 128, false>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
-      return hipGetLastError();
-    case 257:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 128, true>), dim3(nblocks), dim3(WavePlan<128>::NT), 0, s, a);
-      return hipGetLastError();
-    case 512:
-      if (a.stream_out)
-        hipLaunchKernelGGL((stage_wave_kernel<T, 256, false, true>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
-      else
-        hipLaunchKernelGGL((stage_wave_kernel<T, 256, false>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
-      return hipGetLastError();
-    case 513:
-      hipLaunchKernelGGL((stage_wave_kernel<T, 256, true>), dim3(nblocks), dim3(WavePlan<256>::NT), 0, s, a);
-      return hipGetLastError();
-    default:
-      return hipErrorInvalidValue;
+    case 256: return launch_wave_np<T, 128, false>(a, nblocks, s);
+    case 257: return launch_wave_np<T, 128, true>(a, nblocks, s);
+    case 512: return launch_wave_np<T, 256, false>(a, nblocks, s);
+    case 513: return launch_wave_np<T, 256, true>(a, nblocks, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
