@@ -168,3 +168,17 @@ def test_binding_orders_the_handle_stream_against_torch():
     ref = run(None)
     got = run(torch.cuda.Stream())
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_workgroup_sizes_agree_bitwise(precision):
+    """Ten members of a 128x128 depth-6 hierarchy: one group is a launch of
+    2240 tasks (four-wave workgroups), two groups are launches of 1120 (two-
+    wave workgroups, the rule for launches of at most 2048 tasks).  Every
+    task runs the same code, so the two agree bit for bit."""
+    say(f"workgroup sizes {precision}")
+    d = model(nq=128, np_=128, depth=6)
+    ref = run(d, 10, precision, 1, 1, 12, 3)
+    got = run(d, 10, precision, 1, 2, 12, 3)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b), np.max(np.abs(a - b))
