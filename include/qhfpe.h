@@ -166,9 +166,11 @@ double qhfpe_morse_gauss_potential(int32_t j, int32_t l, double x, void* ctx);
  * workgroup owns cells_per_thread consecutive q columns (2, 4 or 8 for FP32
  * two-state; 2 or 4 for FP64 two-state and FP32 three-state; 2 for FP64
  * three-state).  1: the wave-independent variant, one 64-lane wave per
- * 512/np q columns, each lane holding np/64 consecutive p nodes (two states
- * and np = 128 or 256 only).  0 = default: 1 where available, else 4 (2 for
- * three states); it is also the variant at create.  Variants compute the same operations per
+ * task of q columns, each lane holding np/64 consecutive p nodes: two
+ * states at np = 128 or 256 (512/np columns per task); three states with
+ * constant couplings at np = 128, and at np = 256 in FP32 (two columns per
+ * task).  0 = default: 1 where available, else 4 (2 for three states); it
+ * is also the variant at create.  Variants compute the same operations per
  * cell; results agree to rounding (the compiled instruction order and the
  * grouping of the trace partial sums differ).  QHFPE_EUNSUPPORTED if the
  * variant does not exist for this precision, state count and np. */

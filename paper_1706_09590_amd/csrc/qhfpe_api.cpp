@@ -103,7 +103,10 @@ Layout make_layout(const qhfpe_params* p) {
   L.level_elems = L.comp_elems * nc;
   L.member_elems = L.level_elems * (p->depth + 1);
   L.state_bytes = align_up((size_t)L.member_elems * p->batch * L.elem);
-  const int min_tq = plan_groups(p->np) * kMinCpt;
+  const int esz = (p->precision == QHFPE_FP64) ? 8 : 4;
+  const bool wave_ok = wave_variant_supported(esz, p->n_states, p->np);
+  const int min_tq = wave_ok ? std::min(plan_groups(p->np) * kMinCpt, wave_columns_of(p->n_states, p->np))
+                             : plan_groups(p->np) * kMinCpt;
   L.max_tiles = (p->nq + min_tq - 1) / min_tq;
   const long long cells = (long long)(p->depth + 1) * p->nq * p->np;
   const long long pack_blocks = (cells + kBlock - 1) / kBlock;
@@ -129,7 +132,7 @@ Layout make_layout(const qhfpe_params* p) {
   L.off_gtab = off;
   off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
   L.off_mtab = off;
-  if (wave_supported(ns, p->np)) off += align_up((size_t)kWaveTables * L.comp_elems * L.elem);
+  if (wave_ok) off += align_up((size_t)wave_table_planes(ns) * L.comp_elems * L.elem);
   L.off_bath = off;
   off += align_up((size_t)p->batch * kBathStride * sizeof(double));
   L.off_psym = off;
@@ -234,20 +237,29 @@ bool multiplier_tables(const qhfpe_params& p, const Surfaces& U, double dq, doub
 
 // The multiplier tables of the wave variant in one array, each q row
 // permuted so that the n2 values m = k1 + n1 k2 (k2 = 0..n2-1) of row k1
-// are contiguous: dtab 0, dtab 1, the coherence table halved (the kernel
-// treats it as a pair of equal diagonal multipliers), U_01(q + r/2) and
-// U_01(q - r/2) (used only for a q-dependent coupling).
+// are contiguous.  Two states: dtab 0, dtab 1, the coherence table halved
+// (the kernel treats it as a pair of equal diagonal multipliers),
+// U_01(q + r/2) and U_01(q - r/2) (used only for a q-dependent coupling).
+// Three states: dtab 0..2, then the coherence tables of the pairs (0,1),
+// (0,2), (1,2) halved.
 void wave_tables(const qhfpe_params& p, int n1, int n2, const std::vector<double>& dtab,
                  const std::vector<double>& gtab, const std::vector<double>& ctab, std::vector<double>& mtab) {
-  const int nq = p.nq, np = p.np;
+  const int nq = p.nq, np = p.np, ns = p.n_states;
+  const int planes = wave_table_planes(ns);
   const size_t plane = (size_t)nq * np;
-  mtab.assign(kWaveTables * plane, 0.0);
-  for (int t = 0; t < kWaveTables; ++t)
+  mtab.assign(planes * plane, 0.0);
+  for (int t = 0; t < planes; ++t)
     for (int i = 0; i < nq; ++i)
       for (int k1 = 0; k1 < n1; ++k1)
         for (int k2 = 0; k2 < n2; ++k2) {
           const size_t src = (size_t)i * np + k1 + n1 * k2;
-          const double v = (t < 2) ? dtab[t * plane + src] : (t == 2 ? 0.5 * gtab[src] : ctab[(t - 3) * plane + src]);
+          double v;
+          if (t < ns)
+            v = dtab[t * plane + src];
+          else if (ns == 3 || t == 2)
+            v = 0.5 * gtab[(t - ns) * plane + src];
+          else
+            v = ctab[(t - 3) * plane + src];
           mtab[t * plane + (size_t)i * np + (size_t)k1 * n2 + k2] = v;
         }
 }
@@ -356,7 +368,9 @@ struct qhfpe_handle {
   }
 
   bool wave() const { return cpt == kTileWave; }
-  static int tq_of(int np, int code) { return code == kTileWave ? wave_columns(np) : plan_groups(np) * code; }
+  int tq_of(int np, int code) const {
+    return code == kTileWave ? wave_columns_of(ns, np) : plan_groups(np) * code;
+  }
   int tq() const { return tq_of(p.np, cpt); }
   // the trace partials hold L.max_tiles tiles per member and slot: a variant
   // with narrower tiles would index past them
@@ -401,7 +415,7 @@ struct qhfpe_handle {
     a.twiddle2 = twiddle();
     a.dtab = dtab();
     a.gtab = gtab();
-    a.mtab = wave_supported(ns, p.np) ? mtab() : nullptr;
+    a.mtab = wave_variant_supported((int)L.elem, ns, p.np) ? mtab() : nullptr;
     a.qcoup = qcoup;
     a.bath = bath();
     a.psym = psym();
@@ -438,6 +452,7 @@ struct qhfpe_handle {
 
   // waves per workgroup of a wave-variant launch over `batch` members
   int wave_wpb(int batch) const {
+    if (ns == 3) return wave3_wpb((int)L.elem, p.np, (long long)ntiles() * levels * batch);
     return (!qcoup && ntiles() * levels * batch <= kWaveSmallTasks) ? kWaveTasksPerBlockSmall : kWaveTasksPerBlock;
   }
 
@@ -475,6 +490,9 @@ struct qhfpe_handle {
                                           const_cast<void*>(a.closure), L.level_elems, s);
       if (e != hipSuccess) return e;
     }
+    if (wave() && ns == 3)
+      return p.precision == QHFPE_FP64 ? launch_stage_wave3_f64(p.np, a, nblocks, s)
+                                       : launch_stage_wave3_f32(p.np, a, nblocks, s);
     if (wave())
       return p.precision == QHFPE_FP64 ? launch_stage_wave_f64(p.np, a, nblocks, s)
                                        : launch_stage_wave_f32(p.np, a, nblocks, s);
@@ -563,10 +581,9 @@ int install_surfaces(qhfpe_t* h, const Surfaces& U) {
   double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
   if (!multiplier_tables(h->p, U, h->dq, h->dp, dt, gt, ct, &coup_const, coup))
     return fail(QHFPE_EINVAL, "the potential has a non-finite value on the grid");
-  const bool wave_ok = wave_supported(h->ns, h->p.np);
-  if (!coup_const && !wave_ok)
+  if (!coup_const && !wave_supported(h->ns, h->p.np))
     return fail(QHFPE_EUNSUPPORTED, "q-dependent couplings need two states and np = 128 or 256");
-  if (wave_ok) wave_tables(h->p, h->L.n1, h->L.n2, dt, gt, ct, mt);
+  if (wave_variant_supported((int)h->L.elem, h->ns, h->p.np)) wave_tables(h->p, h->L.n1, h->L.n2, dt, gt, ct, mt);
   hipError_t e = hipSuccess;
   auto up = [&](void* dst, const std::vector<double>& src) {
     if (e != hipSuccess || src.empty()) return;

@@ -60,11 +60,30 @@ constexpr int kWaveSmallTasks = 2048;
 inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
 // q columns per task of the wave variant (a lane holds np / 64 p nodes)
 constexpr int wave_columns(int np) { return 512 / np; }
-inline bool tile_supported(int elem_bytes, int ns, int np, int code) {
-  return code == kTileWave ? wave_supported(ns, np) : cpt_supported(elem_bytes, ns, code);
+// The three-state wave variant (stage_wave3.hpp): two q columns per task,
+// np = 128 or 256 in FP32 and np = 128 in FP64 (an FP64 task at np = 256
+// would need 40 KB of LDS), constant couplings only, six multiplier planes.
+constexpr int kWave3Columns = 2;
+constexpr int kWaveTables3 = 6;
+inline bool wave3_supported(int elem_bytes, int np) { return np == 128 || (np == 256 && elem_bytes == 4); }
+inline bool wave_variant_supported(int elem_bytes, int ns, int np) {
+  return ns == 2 ? wave_supported(ns, np) : wave3_supported(elem_bytes, np);
 }
+inline int wave_columns_of(int ns, int np) { return ns == 3 ? kWave3Columns : wave_columns(np); }
+inline int wave_table_planes(int ns) { return ns == 3 ? kWaveTables3 : kWaveTables; }
+// Waves per workgroup of a three-state wave launch of `tasks` tasks: four
+// only for large FP32 launches at np = 128 (elsewhere a four-wave group's
+// LDS would leave room for one group per CU).
+inline int wave3_wpb(int elem_bytes, int np, long long tasks) {
+  return (elem_bytes == 4 && np == 128 && tasks > kWaveSmallTasks) ? kWaveTasksPerBlock : kWaveTasksPerBlockSmall;
+}
+inline bool tile_supported(int elem_bytes, int ns, int np, int code) {
+  return code == kTileWave ? wave_variant_supported(elem_bytes, ns, np) : cpt_supported(elem_bytes, ns, code);
+}
+// the wave variant wherever it exists (three states: 1.3-2.1x faster than
+// the workgroup variant on 128x128 and 256x256 batches of 3-16 members)
 inline int tile_default(int elem_bytes, int ns, int np) {
-  return wave_supported(ns, np) ? kTileWave : cpt_default(elem_bytes, ns);
+  return wave_variant_supported(elem_bytes, ns, np) ? kTileWave : cpt_default(elem_bytes, ns);
 }
 
 // Arguments of the fused RK-stage kernel (passed by value).
@@ -77,7 +96,8 @@ struct StageArgs {
   const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
   const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
   const void* mtab;      // wave variant: [kWaveTables][nq][n1][n2] = dtab 0, dtab 1, gtab / 2, U_01(q + r/2),
-                         // U_01(q - r/2) (both / (hbar np)), entry (k1, k2) at m = k1 + n1 k2
+                         // U_01(q - r/2) (both / (hbar np)), entry (k1, k2) at m = k1 + n1 k2;
+                         // three states: [kWaveTables3][nq][n1][n2] = dtab 0..2, gtab 0..2 / 2
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
   const void* closure;   // wave variant: learned W^(N+1) [B][4][nq][np] (one level per member), or nullptr
@@ -155,6 +175,8 @@ hipError_t launch_stage_f32_ns2(int np, int cpt, const StageArgs& a, int nblocks
 hipError_t launch_stage_f32_ns3(int np, int cpt, const StageArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_stage_wave_f64(int np, const StageArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_stage_wave_f32(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_wave3_f64(int np, const StageArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_stage_wave3_f32(int np, const StageArgs& a, int nblocks, hipStream_t s);
 
 // Pointwise and reduction kernels (aux_kernels.hip).
 struct DipoleMu {
