@@ -83,10 +83,9 @@ typedef struct qhfpe_params {
                                   are dt = T / s with stride s (the response is still sampled
                                   every T). */
   /* U_jl(x) = sum_k poly[j][l][k] x^k.  Diagonal entries: any quartic.
-   * Off-diagonal entries: constants (applied pointwise); a q-dependent
-   * coupling (k >= 1 non-zero) needs two states and np = 128 or 256 (the
-   * wave variant's r-space multiply, see qhfpe_set_potential), else
-   * QHFPE_EUNSUPPORTED.  poly must be symmetric in (j, l). */
+   * Off-diagonal entries: constants (applied pointwise) or q-dependent
+   * (k >= 1 non-zero; applied in the r-space multiply, see
+   * qhfpe_set_potential).  poly must be symmetric in (j, l). */
   double poly[QHFPE_MAX_STATES][QHFPE_MAX_STATES][5];
   double mu[QHFPE_MAX_STATES][QHFPE_MAX_STATES]; /* real symmetric Condon dipole */
 } qhfpe_params;
@@ -138,14 +137,16 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
  * replaces the multipliers of the handle.  fn and ctx are not kept.
  * If every off-diagonal U_jl takes one and the same value at all those
  * points, the coupling is applied pointwise as for a constant polynomial;
- * otherwise it is q-dependent and enters the r-space multiply (mixing the
- * diagonal and coherence blocks), which only the wave variant implements
- * (two states, np = 128 or 256): the handle switches to that variant, and
- * qhfpe_set_tile with a workgroup variant fails until a potential with
+ * otherwise it is q-dependent and enters the r-space multiply, where
+ * -(i/hbar) [U_jl(q + r/2) W_lk - W_jl U_lk(q - r/2)] mixes the diagonal and
+ * coherence transforms of a column.  Two variants implement it: the
+ * two-state wave variant (tile 1, np = 128 or 256) and the workgroup
+ * variant with 2 cells per thread (tile 2, every np, two and three states).
+ * The handle moves to one of them if its variant has no such path, and
+ * qhfpe_set_tile with another variant fails until a potential with
  * constant couplings is set again.  Synchronous.
- * Errors: QHFPE_EINVAL (fn NULL, a non-finite value), QHFPE_EUNSUPPORTED
- * (q-dependent coupling with three states or with np other than 128, 256);
- * on error the handle keeps its previous surfaces. */
+ * Errors: QHFPE_EINVAL (fn NULL, a non-finite value); on error the handle
+ * keeps its previous surfaces. */
 typedef double (*qhfpe_potential_fn)(int32_t j, int32_t l, double x, void* ctx);
 int qhfpe_set_potential(qhfpe_t* h, qhfpe_potential_fn fn, void* ctx);
 
@@ -170,7 +171,8 @@ double qhfpe_morse_gauss_potential(int32_t j, int32_t l, double x, void* ctx);
  * states at np = 128 or 256 (512/np columns per task); three states with
  * constant couplings at np = 128, and at np = 256 in FP32 (two columns per
  * task).  0 = default: 1 where available, else 4 (2 for three states); it
- * is also the variant at create.  Variants compute the same operations per
+ * is also the variant at create.  With a q-dependent coupling only tile 2
+ * and, for two states, tile 1 exist (see qhfpe_set_potential).  Variants compute the same operations per
  * cell; results agree to rounding (the compiled instruction order and the
  * grouping of the trace partial sums differ).  QHFPE_EUNSUPPORTED if the
  * variant does not exist for this precision, state count and np. */

@@ -44,7 +44,7 @@ struct Layout {
   long long member_elems = 0, level_elems = 0, comp_elems = 0;
   size_t state_bytes = 0;
   size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
-  size_t off_dtab = 0, off_gtab = 0, off_mtab = 0, off_bath = 0, off_psym = 0;
+  size_t off_dtab = 0, off_gtab = 0, off_ctab = 0, off_mtab = 0, off_bath = 0, off_psym = 0;
   int n1 = 0, n2 = 0;
   size_t total = 0;
   size_t red_count = 0;
@@ -77,9 +77,6 @@ int validate(const qhfpe_params* p) {
       for (int k = 0; k < 5; ++k) {
         if (!std::isfinite(p->poly[j][l][k])) return fail(QHFPE_EINVAL, "poly has a non-finite entry");
         if (p->poly[j][l][k] != p->poly[l][j][k]) return fail(QHFPE_EINVAL, "poly must be symmetric");
-        if (j != l && k >= 1 && p->poly[j][l][k] != 0.0 && !wave_supported(ns, p->np))
-          return fail(QHFPE_EUNSUPPORTED,
-                      "q-dependent couplings (poly[%d][%d][%d] != 0) need two states and np = 128 or 256", j, l, k);
       }
       if (!std::isfinite(p->mu[j][l]) || p->mu[j][l] != p->mu[l][j])
         return fail(QHFPE_EINVAL, "mu must be finite and symmetric");
@@ -131,6 +128,8 @@ Layout make_layout(const qhfpe_params* p) {
   off += align_up((size_t)ns * L.comp_elems * L.elem);
   L.off_gtab = off;
   off += align_up((size_t)(ns * (ns - 1) / 2) * L.comp_elems * L.elem);
+  L.off_ctab = off;
+  off += align_up((size_t)(ns * (ns - 1)) * L.comp_elems * L.elem);
   L.off_mtab = off;
   if (wave_ok) off += align_up((size_t)wave_table_planes(ns) * L.comp_elems * L.elem);
   L.off_bath = off;
@@ -180,7 +179,7 @@ struct Surfaces {
 // r-space multipliers at (q_i, r_m) for every table the kernels use:
 //   dtab[j] = (U_jj(q + r/2) - U_jj(q - r/2)) / (2 hbar np)
 //   gtab[pair j<k] = (U_jj(q + r/2) - U_kk(q - r/2)) / (hbar np)
-//   ctab[0], ctab[1] = U_01(q + r/2) / (hbar np), U_01(q - r/2) / (hbar np)  (two states)
+//   ctab[2 pair], ctab[2 pair + 1] = U_jk(q + r/2) / (hbar np), U_jk(q - r/2) / (hbar np)
 // Arguments are clamped to the q grid; at the Nyquist column both arguments
 // take the average of the two values.  Returns false if a value is not
 // finite; *coup_const tells whether every off-diagonal U_jl had one value
@@ -195,7 +194,7 @@ bool multiplier_tables(const qhfpe_params& p, const Surfaces& U, double dq, doub
   const size_t plane = (size_t)nq * np;
   dtab.assign((size_t)ns * plane, 0.0);
   gtab.assign((size_t)(ns * (ns - 1) / 2) * plane, 0.0);
-  ctab.assign(ns == 2 ? 2 * plane : 0, 0.0);
+  ctab.assign((size_t)(ns * (ns - 1)) * plane, 0.0);
   double first[QHFPE_MAX_STATES][QHFPE_MAX_STATES] = {};
   bool seen = false, same = true, finite = true;
   for (int i = 0; i < nq; ++i) {
@@ -222,10 +221,12 @@ bool multiplier_tables(const qhfpe_params& p, const Surfaces& U, double dq, doub
       int pr = 0;
       for (int j = 0; j < ns; ++j)
         for (int k = j + 1; k < ns; ++k, ++pr) gtab[pr * plane + at] = (up[j][j] - um[k][k]) / (p.hbar * np);
-      if (ns == 2) {
-        ctab[at] = up[0][1] / (p.hbar * np);
-        ctab[plane + at] = um[0][1] / (p.hbar * np);
-      }
+      pr = 0;
+      for (int j = 0; j < ns; ++j)
+        for (int k = j + 1; k < ns; ++k, ++pr) {
+          ctab[2 * pr * plane + at] = up[j][k] / (p.hbar * np);
+          ctab[(2 * pr + 1) * plane + at] = um[j][k] / (p.hbar * np);
+        }
     }
   }
   *coup_const = same;
@@ -368,6 +369,9 @@ struct qhfpe_handle {
   }
 
   bool wave() const { return cpt == kTileWave; }
+  // variants that take a q-dependent coupling: the two-state wave variant
+  // and the workgroup variant with kQcCpt cells per thread
+  bool qc_variant(int code) const { return code == kTileWave ? ns == 2 : code == kQcCpt; }
   int tq_of(int np, int code) const {
     return code == kTileWave ? wave_columns_of(ns, np) : plan_groups(np) * code;
   }
@@ -386,6 +390,7 @@ struct qhfpe_handle {
   void* twiddle() const { return ws + L.off_tw; }
   void* dtab() const { return ws + L.off_dtab; }
   void* gtab() const { return ws + L.off_gtab; }
+  void* ctab() const { return ws + L.off_ctab; }
   void* mtab() const { return ws + L.off_mtab; }
   double* bath() const { return reinterpret_cast<double*>(ws + L.off_bath); }
   void* psym() const { return ws + L.off_psym; }
@@ -415,6 +420,7 @@ struct qhfpe_handle {
     a.twiddle2 = twiddle();
     a.dtab = dtab();
     a.gtab = gtab();
+    a.ctab = ctab();
     a.mtab = wave_variant_supported((int)L.elem, ns, p.np) ? mtab() : nullptr;
     a.qcoup = qcoup;
     a.bath = bath();
@@ -581,8 +587,6 @@ int install_surfaces(qhfpe_t* h, const Surfaces& U) {
   double coup[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
   if (!multiplier_tables(h->p, U, h->dq, h->dp, dt, gt, ct, &coup_const, coup))
     return fail(QHFPE_EINVAL, "the potential has a non-finite value on the grid");
-  if (!coup_const && !wave_supported(h->ns, h->p.np))
-    return fail(QHFPE_EUNSUPPORTED, "q-dependent couplings need two states and np = 128 or 256");
   if (wave_variant_supported((int)h->L.elem, h->ns, h->p.np)) wave_tables(h->p, h->L.n1, h->L.n2, dt, gt, ct, mt);
   hipError_t e = hipSuccess;
   auto up = [&](void* dst, const std::vector<double>& src) {
@@ -597,12 +601,13 @@ int install_surfaces(qhfpe_t* h, const Surfaces& U) {
   };
   up(h->dtab(), dt);
   up(h->gtab(), gt);
+  up(h->ctab(), ct);
   up(h->mtab(), mt);
   if (e != hipSuccess) return fail(QHFPE_EHIP, "uploading the potential tables: %s", hipGetErrorString(e));
   for (int j = 0; j < QHFPE_MAX_STATES; ++j)
     for (int l = 0; l < QHFPE_MAX_STATES; ++l) h->coup[j][l] = (j < h->ns && l < h->ns) ? coup[j][l] : 0.0;
   h->qcoup = coup_const ? 0 : 1;
-  if (h->qcoup) h->cpt = kTileWave;
+  if (h->qcoup && !h->qc_variant(h->cpt)) h->cpt = wave_supported(h->ns, h->p.np) ? kTileWave : kQcCpt;
   return QHFPE_OK;
 }
 
@@ -740,8 +745,9 @@ int qhfpe_set_tile(qhfpe_t* h, int32_t cells_per_thread) {
   const int c = cells_per_thread == 0 ? tile_default((int)h->L.elem, h->ns, h->p.np) : cells_per_thread;
   if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c))
     return fail(QHFPE_EUNSUPPORTED, "tile variant %d not available for this precision and state count", c);
-  if (h->qcoup && c != kTileWave)
-    return fail(QHFPE_EUNSUPPORTED, "a q-dependent coupling needs the wave variant (tile 1)");
+  if (h->qcoup && !h->qc_variant(c))
+    return fail(QHFPE_EUNSUPPORTED, "a q-dependent coupling needs the two-state wave variant (tile 1) or tile %d",
+                kQcCpt);
   if (h->closure_out && c != kTileWave)
     return fail(QHFPE_EUNSUPPORTED, "a learned closure needs the wave variant (tile 1)");
   h->cpt = c;
@@ -765,7 +771,8 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   int rc = QHFPE_OK;
   for (int c : candidates) {
     if (!tile_supported((int)h->L.elem, h->ns, h->p.np, c) || !h->tile_fits(c)) continue;
-    if ((h->qcoup || h->closure_out) && c != kTileWave) continue;
+    if (h->closure_out && c != kTileWave) continue;
+    if (h->qcoup && !h->qc_variant(c)) continue;
     h->cpt = c;
     StageArgs a = h->stage_args(h->y(), h->y(), h->va(), 0.25 * h->p.dt);
     hipError_t e = h->launch(a);  // warm-up

@@ -36,6 +36,9 @@ inline const Plan* find_plan(int np) {
 // three-state; 2 for FP64 three-state (larger LDS tiles would not fit).
 constexpr int plan_groups(int np) { return np >= 256 ? 1 : 256 / np; }
 constexpr int kMinCpt = 2;
+// The workgroup variant with a q-dependent coupling (the coupling surfaces
+// in the r-space multiply) exists for 2 cells per thread only.
+constexpr int kQcCpt = 2;
 constexpr bool cpt_supported_c(int elem_bytes, int ns, int cpt) {
   return (ns == 2) ? (cpt == 2 || cpt == 4 || (cpt == 8 && elem_bytes == 4))
                    : (elem_bytes == 8 ? cpt == 2 : (cpt == 2 || cpt == 4));
@@ -95,6 +98,8 @@ struct StageArgs {
   const void* twiddle2;  // [n1][n2+1] complex exp(+2 pi i (n2 k1 mod np)/np), state precision
   const void* dtab;      // [ns][nq][np]: (U_j(q+r/2) - U_j(q-r/2)) / (2 hbar np), 0 at Nyquist
   const void* gtab;      // [npair][nq][np]: (U_j(q+r/2) - U_k(q-r/2)) / (hbar np), j < k
+  const void* ctab;      // [npair][2][nq][np]: U_jl(q + r/2), U_jl(q - r/2) / (hbar np), pair j < l
+                         // (q-dependent couplings in the workgroup variant)
   const void* mtab;      // wave variant: [kWaveTables][nq][n1][n2] = dtab 0, dtab 1, gtab / 2, U_01(q + r/2),
                          // U_01(q - r/2) (both / (hbar np)), entry (k1, k2) at m = k1 + n1 k2;
                          // three states: [kWaveTables3][nq][n1][n2] = dtab 0..2, gtab 0..2 / 2

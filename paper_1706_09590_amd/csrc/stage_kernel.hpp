@@ -17,7 +17,9 @@
 // in the conjugate r-space, and the inverse two-pass FFT.  Diagonal
 // potentials are r-dependent (U(q + r/2) - U(q - r/2)), so they go through
 // the transform; two real diagonal components share one complex transform.
-// The constant diabatic couplings are a pointwise commutator in p-space.
+// The constant diabatic couplings are a pointwise commutator in p-space; a
+// q-dependent coupling (the QC instantiation, 2 cells per thread) enters
+// the r-space multiply instead, where it mixes the transforms of a column.
 //
 // State layout (packed reals): [member][level][comp][q][p], p fastest.
 #pragma once
@@ -78,7 +80,69 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nblocks) {
   return (bid % kXcd) * per + bid / kXcd;
 }
 
-template <typename T, int NS, int NP, int CPT_>
+// q-dependent couplings (QC instantiation).  The r-space matrix of one tile
+// column at index m: the diagonals separated from their packed transforms
+// (H_00 + i H_11 of the column; for three states H_22 from the transform
+// that packs the W22 of the column pair c & ~1, c | 1), the coherences
+// H_jk (j < k) from their own transforms, and H_kj(m) = conj H_jk(-m).
+// pm, pp: LDS positions of m and -m within a column.
+template <typename T, int NS>
+__device__ __forceinline__ void rspace_matrix(const T* sv, int ldp, int c, int pm, int pp, cx<T> (&H)[NS][NS]) {
+  constexpr int NC = NS * NS;
+  const T* d0 = sv + (c * NC + 0) * ldp;
+  const T* d1 = d0 + ldp;
+  {
+    const cx<T> z = {d0[pm], d1[pm]}, zc = {d0[pp], -d1[pp]};  // Z(m), conj Z(-m)
+    H[0][0] = {T(0.5) * (z.re + zc.re), T(0.5) * (z.im + zc.im)};
+    H[1][1] = {T(0.5) * (z.im - zc.im), T(-0.5) * (z.re - zc.re)};  // (Z - conj Z(-m)) / 2i
+  }
+  if constexpr (NS == 3) {
+    const T* a2 = sv + ((c & ~1) * NC + 2) * ldp;
+    const T* b2 = sv + ((c | 1) * NC + 2) * ldp;
+    const cx<T> z = {a2[pm], b2[pm]}, zc = {a2[pp], -b2[pp]};
+    H[2][2] = (c & 1) ? cx<T>{T(0.5) * (z.im - zc.im), T(-0.5) * (z.re - zc.re)}
+                      : cx<T>{T(0.5) * (z.re + zc.re), T(0.5) * (z.im + zc.im)};
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+#pragma unroll
+    for (int k = j + 1; k < NS; ++k) {
+      const T* r = sv + (c * NC + Packing<NS>::re(j, k)) * ldp;
+      const T* i = r + ldp;
+      H[j][k] = {r[pm], i[pm]};
+      H[k][j] = {r[pp], -i[pp]};
+    }
+}
+
+// The coupling part of the potential term in r space at one column and m:
+//   C_jk = -i [ sum_{l != j} up_jl H_lk - sum_{l != k} H_jl um_lk ]
+// with up_jl = U_jl(q + r/2) / (hbar np), um_jl = U_jl(q - r/2) / (hbar np)
+// (off-diagonal surfaces only; the diagonal ones are in the multipliers).
+template <typename T, int NS>
+__device__ __forceinline__ cx<T> coupling_rspace(const cx<T> (&H)[NS][NS], const T (&up)[NS][NS],
+                                                 const T (&um)[NS][NS], int j, int k) {
+  cx<T> s = {T(0), T(0)};
+#pragma unroll
+  for (int jj = 0; jj < NS; ++jj)
+#pragma unroll
+    for (int kk = 0; kk < NS; ++kk) {
+      if (jj != j || kk != k) continue;
+#pragma unroll
+      for (int l = 0; l < NS; ++l) {
+        if (l != jj) {
+          s.re += up[jj][l] * H[l][kk].re;
+          s.im += up[jj][l] * H[l][kk].im;
+        }
+        if (l != kk) {
+          s.re -= H[jj][l].re * um[l][kk];
+          s.im -= H[jj][l].im * um[l][kk];
+        }
+      }
+    }
+  return {s.im, -s.re};
+}
+
+template <typename T, int NS, int NP, int CPT_, bool QC = false>
 __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel(StageArgs a) {
   using P = PlanOf<T, NS, NP, CPT_>;
   constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ, NT = P::NT, CPT = P::CPT;
@@ -435,6 +499,23 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
     const T* pi = im + pbase;
     const T* sy = ssym + k1;
     cx<T> y[N2];
+    // QC: the coupling surfaces of the transform's column(s) at this row
+    const unsigned tb = (unsigned)((long long)nq * NP * ES);
+    const rsrc_t rct = make_rsrc(a.ctab, QC ? 2u * NPAIR * tb : 0u);
+    const int qA = min(q0 + colA, nq - 1), qB = min(q0 + colB, nq - 1);
+    auto surfaces = [&](int q, int k2, T (&up)[NS][NS], T (&um)[NS][NS]) {
+      const unsigned off = ((unsigned)q * NP + (unsigned)(k1 + N1 * k2)) * ES;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        up[j][j] = um[j][j] = T(0);
+#pragma unroll
+        for (int k = j + 1; k < NS; ++k) {
+          const int pr = Packing<NS>::pair(j, k);
+          up[j][k] = up[k][j] = buf_load<T>(rct, off, (2 * pr) * tb);
+          um[j][k] = um[k][j] = buf_load<T>(rct, off, (2 * pr + 1) * tb);
+        }
+      }
+    };
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const cx<T> z = {zr[k2], zi[k2]};
@@ -450,6 +531,27 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
         // Y = -i g Z
         const T gg = mulA[t][k2];
         y[k2] = {gg * z.im + e * z.re, -gg * z.re + e * z.im};
+      }
+      if constexpr (QC) {
+        const int pm = (N2 + 1) * k1 + k2, pp = pbase - k2;
+        cx<T> H[NS][NS];
+        T up[NS][NS], um[NS][NS];
+        rspace_matrix<T, NS>(sv, LDP, colA, pm, pp, H);
+        surfaces(qA, k2, up, um);
+        if (kind == 1) {
+          y[k2] = y[k2] + coupling_rspace<T, NS>(H, up, um, d.sj, d.sk);
+        } else if (d.sj == 0) {
+          // packed diagonals of one column: C_00 + i C_11
+          const cx<T> c00 = coupling_rspace<T, NS>(H, up, um, 0, 0), c11 = coupling_rspace<T, NS>(H, up, um, 1, 1);
+          y[k2] = y[k2] + cx<T>{c00.re - c11.im, c00.im + c11.re};
+        } else {
+          // W22 of two columns: C_22 of colA + i C_22 of colB
+          const cx<T> ca = coupling_rspace<T, NS>(H, up, um, NS - 1, NS - 1);
+          rspace_matrix<T, NS>(sv, LDP, colB, pm, pp, H);
+          surfaces(qB, k2, up, um);
+          const cx<T> cb2 = coupling_rspace<T, NS>(H, up, um, NS - 1, NS - 1);
+          y[k2] = y[k2] + cx<T>{ca.re - cb2.im, ca.im + cb2.re};
+        }
       }
     }
     SmallDft<N2, -1, T>::run(y);
@@ -529,18 +631,20 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   }
 }
 
-template <typename T, int NS, int NP, int CPT>
+template <typename T, int NS, int NP, int CPT, bool QC = false>
 hipError_t launch_stage_variant(const StageArgs& a, int nblocks, hipStream_t s) {
   if constexpr (cpt_supported_c((int)sizeof(T), NS, CPT)) {
-    hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT, QC>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0, s, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
+// a q-dependent coupling has one variant, kQcCpt cells per thread
 template <typename T, int NS, int NP>
 hipError_t launch_stage_np(int cpt, const StageArgs& a, int nblocks, hipStream_t s) {
+  if (a.qcoup) return cpt == kQcCpt ? launch_stage_variant<T, NS, NP, kQcCpt, true>(a, nblocks, s) : hipErrorInvalidValue;
   switch (cpt) {
     case 2:
       return launch_stage_variant<T, NS, NP, 2>(a, nblocks, s);

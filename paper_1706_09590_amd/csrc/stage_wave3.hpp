@@ -60,8 +60,8 @@ __device__ __forceinline__ constexpr int wave3_slot(int i, int comp) {
   return comp < 2 ? 8 * i + comp : (comp == 2 ? 16 + i : 8 * i + comp - 1);
 }
 
-// Waves per SIMD the register allocation aims at: three for FP32 at
-// np = 128, two otherwise (LDS allows no more).
+// Waves per SIMD the register allocation aims at (the second launch bound):
+// three for FP32 at np = 128, two otherwise (LDS allows no more).
 template <typename T, int NP>
 constexpr int wave3_waves_per_simd() {
   return (sizeof(T) == 4 && NP == 128) ? 3 : 2;
@@ -70,7 +70,7 @@ constexpr int wave3_waves_per_simd() {
 // NTS: non-temporal output stores (StageArgs::stream_out).  WPB: waves per
 // workgroup (StageArgs::wpb).
 template <typename T, int NP, bool NTS, int WPB_>
-__global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (4 * wave3_waves_per_simd<T, NP>()) / WPB_)
+__global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_simd<T, NP>()))
     stage_wave3_kernel(StageArgs a) {
   using W = WavePlan3<NP, WPB_>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;

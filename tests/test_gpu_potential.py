@@ -200,35 +200,6 @@ def test_polynomial_function_reproduces_params_poly():
     assert np.array_equal(out[0], out[1])
 
 
-def test_q_dependent_coupling_needs_the_wave_variant():
-    d = small(np_=128, nq=16, depth=1)
-    P = qhfpe.Propagator(d, batch=1, precision="fp64")
-    try:
-        P.set_tile(4)
-        P.set_potential_morse_gauss(**MG)  # switches to the wave variant
-        with pytest.raises(qhfpe.QHFPEError):
-            P.set_tile(4)
-        P.set_tile(1)
-        assert P.autotune(2) == 1
-    finally:
-        P.close()
-    # no wave variant at np = 64, nor for three states
-    qdep = lambda j, l, x: 0.5 * x * x + j if j == l else 0.1 * x  # noqa: E731
-    for bad in (small(np_=64, nq=16, depth=1),
-                inputs.model_dict(small(np_=128, nq=16, depth=1), n_states=3,
-                                  poly=inputs.three_state_surfaces(0.3, 0.2),
-                                  mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])):
-        P = qhfpe.Propagator(bad, batch=1, precision="fp64")
-        try:
-            with pytest.raises(qhfpe.QHFPEError) as e:
-                P.set_potential(qdep)
-            assert e.value.code == qhfpe.EUNSUPPORTED
-            # a constant coupling is fine on every shape
-            P.set_potential(lambda j, l, x: 0.5 * x * x + j if j == l else 0.2)
-        finally:
-            P.close()
-
-
 def test_non_finite_potential_is_rejected_and_keeps_the_old_surfaces():
     d = small(np_=128, nq=16, depth=1)
     W = inputs.random_hierarchy(1, 2, 16, 128, seed=72)

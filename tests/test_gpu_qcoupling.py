@@ -1,0 +1,193 @@
+"""q-dependent diabatic couplings U_jl(q) (Eq. (system-Hamiltonian); the
+coupling part of Eq. (quantum-liouvillian) in r space) in the workgroup
+variant: every FFT plan, two and three states, against the FP64 oracle with
+the same surfaces, and against the two-state wave variant.
+
+Bars as elsewhere: one operator application FP64 relative L2 <= 1e-12,
+FP32 <= 1e-5; variants agree to 1e-13 after a propagation.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import oracle_model
+from oracle import qhfpe_oracle as O
+from paper_1706_09590_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1706_09590_amd import qhfpe  # noqa: E402
+
+QC_TILE = 2
+WAVE = 1
+MG = dict(D0=3.0, D1=2.5, a0=0.4, a1=0.5, q0=-0.3, q1=0.8, dE=0.7, dV=0.45, qs=0.4, sigma=0.9)
+MU3 = [[0.1, 1.0, 0.4], [1.0, -0.2, 0.7], [0.4, 0.7, 0.3]]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+def model(ns=2, np_=64, nq=13, depth=2, **kw):
+    base = inputs.SMALL_ABSORPTION["model"]
+    if ns == 2:
+        return inputs.model_dict(base, nq=nq, np=np_, depth=depth, dt=0.001, **kw)
+    return inputs.model_dict(base, n_states=3, nq=nq, np=np_, depth=depth, dt=0.001, poly=three_state_qpoly(),
+                             mu=MU3, **kw)
+
+
+def three_state_qpoly():
+    """The three-state quartic diagonals with a quadratic coupling on every
+    pair (different on each, so that a coupling landing in the wrong
+    component cannot hide)."""
+    poly = inputs.three_state_surfaces(0.0, 0.0)
+    for (j, l), c in (((0, 1), [0.3, 0.1, 0.02, 0, 0]), ((0, 2), [0.15, -0.05, 0.01, 0, 0]),
+                      ((1, 2), [0.2, 0.08, -0.015, 0, 0])):
+        poly[j][l] = list(c)
+        poly[l][j] = list(c)
+    return poly
+
+
+def gauss3(j, l, x):
+    """Three-state surfaces with Gaussian couplings of different centres."""
+    if j == l:
+        return 0.5 * (x - (-1.0, 0.5, 1.5)[j]) ** 2 + (0.0, 7.0, 6.0)[j]
+    k = (j, l) if j < l else (l, j)
+    amp, cen = {(0, 1): (0.4, 0.2), (0, 2): (0.25, -0.8), (1, 2): (0.3, 1.1)}[k]
+    return amp * np.exp(-((x - cen) ** 2) / 0.8)
+
+
+def gauss3_array(x):
+    x = np.asarray(x, dtype=np.float64)
+    return np.array([[gauss3(j, l, x) for l in range(3)] for j in range(3)])
+
+
+def rhs_case(d, precision, seed, phase=0, tile=QC_TILE, setup=None, oracle_fn=None):
+    ns = d["n_states"]
+    W = inputs.random_hierarchy(d["depth"], ns, d["nq"], d["np"], seed=seed, phase=phase)
+    P = qhfpe.Propagator(d, batch=1, precision=precision)
+    try:
+        if setup is not None:
+            setup(P)
+        P.set_tile(tile)
+        P.set_state(torch.from_numpy(W[None]), phase=phase)
+        P.apply_rhs()
+        got = P.get_state().cpu().numpy()[0]
+    finally:
+        P.close()
+    m = oracle_model(d)
+    if oracle_fn is not None:
+        m.potential_fn = oracle_fn
+    return rel(got, O.rhs(m, W))
+
+
+@pytest.mark.parametrize("np_", [24, 64, 96, 128, 192, 256])
+@pytest.mark.parametrize("phase", [0, 1])
+def test_two_state_morse_gauss_workgroup_variant(np_, phase):
+    """The Morse/Gaussian surfaces of Sec. III on the workgroup variant, at
+    shapes the wave variant does not have and at the two it has."""
+    say(f"qc workgroup two states np={np_} phase={phase}")
+    d = model(ns=2, np_=np_, nq=13, depth=2)
+    err = rhs_case(d, "fp64", seed=800 + np_ + phase, phase=phase,
+                   setup=lambda P: P.set_potential_morse_gauss(**MG), oracle_fn=O.paper_surfaces(**MG))
+    assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("np_,nq,depth", [(24, 13, 2), (64, 8, 0), (128, 13, 1), (192, 9, 2), (256, 7, 1)])
+@pytest.mark.parametrize("phase", [0, 1])
+def test_three_state_polynomial_couplings(np_, nq, depth, phase):
+    """Quadratic couplings on every pair of three states from params.poly
+    (odd nq: the last tile's W22 transform pairs a column with a ghost)."""
+    say(f"qc three states np={np_} nq={nq} depth={depth} phase={phase}")
+    err = rhs_case(model(ns=3, np_=np_, nq=nq, depth=depth), "fp64", seed=820 + np_ + nq + phase, phase=phase)
+    assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_state_gaussian_couplings_from_a_function(precision):
+    say(f"qc three states, Gaussian couplings, {precision}")
+    d = model(ns=3, np_=128, nq=15, depth=2)
+    err = rhs_case(d, precision, seed=840, setup=lambda P: P.set_potential(gauss3), oracle_fn=gauss3_array)
+    assert err < (1e-12 if precision == "fp64" else 1e-5), err
+
+
+@pytest.mark.parametrize("np_", [128, 256])
+def test_workgroup_variant_agrees_with_wave_variant(np_):
+    """Two members of different baths, Morse/Gaussian surfaces, twelve
+    steps with traces every three."""
+    say(f"qc workgroup vs wave np={np_}")
+    d = model(ns=2, np_=np_, nq=20, depth=3)
+    out = {}
+    for tile in (QC_TILE, WAVE):
+        P = qhfpe.Propagator(d, batch=2, precision="fp64")
+        P.set_member_bath(1, 1.0, 0.8, 0.7)
+        P.set_potential_morse_gauss(**MG)
+        P.set_tile(tile)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        out[tile] = (P.step(12, 3).cpu().numpy(), P.get_state().cpu().numpy())
+        P.close()
+    assert rel(out[WAVE][1], out[QC_TILE][1]) < 1e-13
+    assert rel(out[WAVE][0], out[QC_TILE][0]) < 1e-13
+
+
+def test_three_state_propagation_parity():
+    """Twelve RK4 steps of a three-state member with q-dependent couplings
+    against the oracle's propagation."""
+    say("qc three states propagation")
+    d = model(ns=3, np_=64, nq=12, depth=2)
+    m = oracle_model(d)
+    W = inputs.random_hierarchy(2, 3, 12, 64, seed=850)
+    P = qhfpe.Propagator(d, batch=1, precision="fp64")
+    try:
+        P.set_state(torch.from_numpy(W[None]))
+        P.step(12, 1, record=False)
+        got = P.get_state().cpu().numpy()[0]
+    finally:
+        P.close()
+    tables = O.moyal_tables(m)
+    ref = W
+    for _ in range(12):
+        ref = O.rk4_step(m, ref, tables=tables)
+    assert rel(got, ref) < 1e-11
+
+
+def test_variants_that_take_a_q_dependent_coupling():
+    """Two states: the wave variant and the workgroup variant with two cells
+    per thread; three states: the workgroup variant only (the three-state
+    wave variant has constant couplings)."""
+    d2 = model(ns=2, np_=128, nq=16, depth=1)
+    P = qhfpe.Propagator(d2, batch=1, precision="fp64")
+    try:
+        P.set_tile(4)
+        P.set_potential_morse_gauss(**MG)  # moves to a variant that has it
+        with pytest.raises(qhfpe.QHFPEError):
+            P.set_tile(4)
+        P.set_tile(QC_TILE)
+        P.set_tile(WAVE)
+        assert P.autotune(2) in (WAVE, QC_TILE)
+    finally:
+        P.close()
+    d3 = model(ns=3, np_=128, nq=16, depth=1)
+    P = qhfpe.Propagator(d3, batch=1, precision="fp64")
+    try:
+        with pytest.raises(qhfpe.QHFPEError):
+            P.set_tile(WAVE)
+        assert P.autotune(2) == QC_TILE
+        # a constant coupling brings the three-state wave variant back
+        P.set_potential(lambda j, l, x: 0.5 * x * x + j if j == l else 0.2)
+        P.set_tile(WAVE)
+    finally:
+        P.close()

@@ -37,8 +37,6 @@ def test_workspace_bytes_scales_with_batch_and_precision():
     (dict(dt=0.0), qhfpe.EINVAL),
     (dict(q_min=1.0, q_max=1.0), qhfpe.EINVAL),
     (dict(beta=10.0), qhfpe.EUNSUPPORTED),         # beta hbar gamma >= 2 pi with the correction
-    (dict(poly=[[[0, 0, .5, 0, 0], [0.3, 0.1, 0, 0, 0]], [[0.3, 0.1, 0, 0, 0], [1, 0, .5, 0, 0]]]),
-     qhfpe.EUNSUPPORTED),                            # q-dependent coupling
     (dict(poly=[[[0, 0, .5, 0, 0], [0.3, 0, 0, 0, 0]], [[0.2, 0, 0, 0, 0], [1, 0, .5, 0, 0]]]),
      qhfpe.EINVAL),                                  # not symmetric
     (dict(mu=[[0, 1], [0.5, 0]]), qhfpe.EINVAL),
@@ -51,14 +49,19 @@ def test_parameter_validation(override, code):
     assert qhfpe.lib().qhfpe_last_error().decode() != ""
 
 
-def test_q_dependent_polynomial_coupling_accepted_where_the_wave_variant_exists():
+def test_q_dependent_polynomial_coupling_accepted_on_every_shape():
+    """The workgroup variant takes a q-dependent coupling at every np and
+    for three states, the two-state wave variant at np = 128 and 256."""
     qc = [[[0, 0, .5, 0, 0], [0.3, 0.1, 0.02, 0, 0]], [[0.3, 0.1, 0.02, 0, 0], [1, 0, .5, 0, 0]]]
-    for np_ in (128, 256):
+    for np_ in (24, 64, 128, 192, 256):
         m = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], np=np_, poly=qc)
         assert qhfpe.workspace_bytes(m) > 0
-    with pytest.raises(qhfpe.QHFPEError) as ei:
-        qhfpe.workspace_bytes(inputs.model_dict(inputs.SMALL_ABSORPTION["model"], np=64, poly=qc))
-    assert ei.value.code == qhfpe.EUNSUPPORTED
+    z = [0.0] * 5
+    qc3 = [[[0, 0, .5, 0, 0], [0.3, 0.1, 0, 0, 0], z], [[0.3, 0.1, 0, 0, 0], [1, 0, .5, 0, 0], [0.2, 0, 0.01, 0, 0]],
+           [z, [0.2, 0, 0.01, 0, 0], [2, 0, .5, 0, 0]]]
+    m = inputs.model_dict(inputs.SMALL_ABSORPTION["model"], n_states=3, np=96, poly=qc3,
+                          mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])
+    assert qhfpe.workspace_bytes(m) > 0
 
 
 def test_morse_gauss_surfaces_on_the_host():
