@@ -78,13 +78,14 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
 
 // QC: q-dependent diabatic coupling U_01(q), applied in the r-space multiply
 // (it mixes the packed-diagonal and coherence transforms of a column).
-// Occupancy: FP32 without QC is held to four waves per SIMD (128 VGPRs); the
-// others run two (FP64: 79 KB of LDS per workgroup allows no more).
+// Occupancy (the second launch bound, waves per SIMD): FP32 without QC is
+// held to four waves per SIMD (128 VGPRs); the others run two (FP64: 79 KB
+// of LDS per four-wave workgroup allows no more).
 // NTS: non-temporal output stores (the launcher picks it when the state
 // arrays exceed the memory-side cache, StageArgs::stream_out).  WPB: waves
 // per workgroup (StageArgs::wpb).
 template <typename T, int NP, bool QC, bool NTS = false, int WPB_ = kWaveTasksPerBlock>
-__global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !QC ? 16 : 8) / WPB_)
+__global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !QC ? 4 : 2))
     stage_wave_kernel(StageArgs a) {
   using W = WavePlan<NP, WPB_>;
   constexpr int N1 = W::N1, N2 = W::N2, K = W::K, C = W::C, NC = W::NC, WPB = W::WPB;
