@@ -155,3 +155,37 @@ def test_wave3_availability():
         with pytest.raises(qhfpe.QHFPEError):
             P.set_tile(WAVE)
         P.close()
+
+
+def test_wave3_streaming_stores_bitwise():
+    """Four three-state 256x256 depth-10 members in FP32: the three state
+    arrays (311 MB) exceed the memory-side cache, so the stage stores are
+    non-temporal; each member alone (78 MB) uses plain stores.  Same kernel
+    arithmetic, so bit-identical states and traces."""
+    say("wave3 non-temporal stores vs plain")
+    d = model(nq=256, depth=10, np_=256)
+    baths = [(0.3, 1.0, 1.0), (0.6, 0.8, 1.2), (0.9, 1.1, 0.9), (0.45, 0.7, 1.0)]
+    P = qhfpe.Propagator(d, batch=4, precision="fp32")
+    try:
+        for b, bath in enumerate(baths):
+            P.set_member_bath(b, *bath)
+        P.set_tile(WAVE)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        tr4 = P.step(2, 1).cpu().numpy()
+        st4 = P.get_state().cpu().numpy()
+    finally:
+        P.close()
+    for b, bath in enumerate(baths):
+        P = qhfpe.Propagator(d, batch=1, precision="fp32")
+        try:
+            P.set_member_bath(0, *bath)
+            P.set_tile(WAVE)
+            P.init_thermal(1.0)
+            P.apply_dipole()
+            tr1 = P.step(2, 1).cpu().numpy()
+            st1 = P.get_state().cpu().numpy()
+        finally:
+            P.close()
+        np.testing.assert_array_equal(st1[0], st4[b])
+        np.testing.assert_array_equal(tr1[0], tr4[b])
