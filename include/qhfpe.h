@@ -150,6 +150,21 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
 typedef double (*qhfpe_potential_fn)(int32_t j, int32_t l, double x, void* ctx);
 int qhfpe_set_potential(qhfpe_t* h, qhfpe_potential_fn fn, void* ctx);
 
+/* Potential surfaces given as the r-space tables of Eq.
+ * (quantum-liouvillian) themselves: u_plus[j][l][i][m] = U_jl(q_i + r_m/2)
+ * and u_minus[j][l][i][m] = U_jl(q_i - r_m/2), host FP64 arrays of
+ * n_states x n_states x nq x np, row-major, with r_m = mh dr, dr =
+ * 2 pi hbar / (np dp) and mh = m for m <= np/2, m - np above (the DFT order
+ * of the transform along p).  Only the entries with j <= l are read (U_lj =
+ * U_jl is implied).  The values are used as given: clamping the arguments
+ * to the grid and the Nyquist column are the caller's (qhfpe_set_potential
+ * applies the library's readings).  Couplings, variants and errors as for
+ * qhfpe_set_potential: constant off-diagonal tables take the pointwise path,
+ * anything else the r-space one.  The arrays are read during this call
+ * only.  Synchronous.  Errors: QHFPE_EINVAL (NULL array, a non-finite
+ * value); on error the handle keeps its previous surfaces. */
+int qhfpe_set_potential_tables(qhfpe_t* h, const double* u_plus, const double* u_minus);
+
 /* The two-state surfaces of Sec. III in the dimensionless coordinate:
  *   U_00 = D0 (1 - exp(-a0 (x - q0)))^2
  *   U_11 = D1 (1 - exp(-a1 (x - q1)))^2 + dE

@@ -165,11 +165,15 @@ double poly_value(const double* c, double x) {
 
 // r-space multipliers of the potential term at (q_i, r_m), with the argument
 // q +- r/2 clamped to the q-grid and the Nyquist column averaged over +-r.
-// Surfaces U_jl(x), j <= l: the params' polynomials or a host function.
+// Surfaces U_jl(x), j <= l: the params' polynomials or a host function; or
+// the caller's tables of U_jl(q_i +- r_m/2) themselves ([ns][ns][nq][np],
+// used as given).
 struct Surfaces {
   const qhfpe_params* p = nullptr;
   qhfpe_potential_fn fn = nullptr;
   void* ctx = nullptr;
+  const double* up_tab = nullptr;
+  const double* um_tab = nullptr;
   double operator()(int j, int l, double x) const {
     if (fn) return fn(j, l, x, ctx);
     return poly_value(p->poly[j][l], x);
@@ -206,10 +210,16 @@ bool multiplier_tables(const qhfpe_params& p, const Surfaces& U, double dq, doub
       double up[QHFPE_MAX_STATES][QHFPE_MAX_STATES], um[QHFPE_MAX_STATES][QHFPE_MAX_STATES];
       for (int j = 0; j < ns; ++j)
         for (int l = j; l < ns; ++l) {
-          up[j][l] = U(j, l, xp);
-          um[j][l] = U(j, l, xm);
+          if (U.up_tab) {
+            const size_t t = (((size_t)j * ns + l) * nq + i) * np + m;
+            up[j][l] = U.up_tab[t];
+            um[j][l] = U.um_tab[t];
+          } else {
+            up[j][l] = U(j, l, xp);
+            um[j][l] = U(j, l, xm);
+          }
           finite = finite && std::isfinite(up[j][l]) && std::isfinite(um[j][l]);
-          if (nyq) up[j][l] = um[j][l] = 0.5 * (up[j][l] + um[j][l]);
+          if (nyq && !U.up_tab) up[j][l] = um[j][l] = 0.5 * (up[j][l] + um[j][l]);
           if (l > j) {
             if (!seen) first[j][l] = up[j][l];
             same = same && up[j][l] == first[j][l] && um[j][l] == first[j][l];
@@ -695,6 +705,16 @@ int qhfpe_set_potential(qhfpe_t* h, qhfpe_potential_fn fn, void* ctx) {
   U.p = &h->p;
   U.fn = fn;
   U.ctx = ctx;
+  return install_surfaces(h, U);
+}
+
+int qhfpe_set_potential_tables(qhfpe_t* h, const double* u_plus, const double* u_minus) {
+  if (int rc = check_handle(h)) return rc;
+  if (!u_plus || !u_minus) return fail(QHFPE_EINVAL, "u_plus and u_minus must not be NULL");
+  Surfaces U;
+  U.p = &h->p;
+  U.up_tab = u_plus;
+  U.um_tab = u_minus;
   return install_surfaces(h, U);
 }
 

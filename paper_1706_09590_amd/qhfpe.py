@@ -85,6 +85,7 @@ def lib():
         "qhfpe_autotune": ([_vp, _c_i32, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_set_streams": ([_vp, _c_i32], _c_int),
         "qhfpe_set_potential": ([_vp, _vp, _vp], _c_int),
+        "qhfpe_set_potential_tables": ([_vp, _vp, _vp], _c_int),
         "qhfpe_morse_gauss_potential": ([_c_i32, _c_i32, _c_dbl, _vp], _c_dbl),
         "qhfpe_get_streams": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_init_thermal": ([_vp, _c_dbl, _vp], _c_int),
@@ -255,6 +256,18 @@ class Propagator:
         multipliers (qhfpe_set_potential)."""
         cb = POTENTIAL_FN(lambda j, l, x, ctx: float(fn(j, l, x)))
         _check(lib().qhfpe_set_potential(self.handle, ctypes.cast(cb, _vp), None))
+
+    def set_potential_tables(self, u_plus, u_minus):
+        """Surfaces as the r-space tables U_jl(q_i +- r_m/2), host arrays of
+        shape (n_states, n_states, nq, np) in DFT order along m, used as
+        given (qhfpe_set_potential_tables)."""
+        import numpy as np
+        shape = (self.model["n_states"],) * 2 + (self.model["nq"], self.model["np"])
+        up = np.ascontiguousarray(u_plus, dtype=np.float64)
+        um = np.ascontiguousarray(u_minus, dtype=np.float64)
+        if up.shape != shape or um.shape != shape:
+            raise ValueError(f"u_plus and u_minus must have shape {shape}")
+        _check(lib().qhfpe_set_potential_tables(self.handle, up.ctypes.data_as(_vp), um.ctypes.data_as(_vp)))
 
     def set_potential_morse_gauss(self, **params):
         """The Morse/Gaussian surfaces of Sec. III, evaluated by the library's

@@ -191,3 +191,63 @@ def test_variants_that_take_a_q_dependent_coupling():
         P.set_tile(WAVE)
     finally:
         P.close()
+
+
+def test_potential_tables_given_directly():
+    """Surfaces given as the r-space tables U_jl(q_i +- r_m/2) themselves
+    (qhfpe_set_potential_tables; here the oracle's own tables, clamped and
+    Nyquist-averaged): two states on the wave variant, three states on the
+    workgroup variant, against the oracle with those tables."""
+    cases = ((model(ns=2, np_=128, nq=14, depth=2), O.paper_surfaces(**MG), WAVE),
+             (model(ns=3, np_=96, nq=11, depth=1), gauss3_array, QC_TILE))
+    for d, fn, tile in cases:
+        say(f"potential tables ns={d['n_states']} np={d['np']}")
+        m = oracle_model(d)
+        m.potential_fn = fn
+        up, um = O.moyal_tables(m)
+        W = inputs.random_hierarchy(d["depth"], d["n_states"], d["nq"], d["np"], seed=860 + d["np"])
+        P = qhfpe.Propagator(d, batch=1, precision="fp64")
+        try:
+            P.set_potential_tables(up, um)
+            P.set_tile(tile)
+            P.set_state(torch.from_numpy(W[None]))
+            P.apply_rhs()
+            got = P.get_state().cpu().numpy()[0]
+        finally:
+            P.close()
+        assert rel(got, O.rhs(m, W, tables=(up, um))) < 1e-12
+
+
+def test_constant_coupling_tables_take_the_pointwise_path():
+    """Tables of the quartic model with its constant coupling: the library
+    recognises the constant off-diagonal tables, so every workgroup variant
+    stays available, and the result equals the params.poly path."""
+    say("constant-coupling tables")
+    d = model(ns=2, np_=64, nq=12, depth=2)
+    m = oracle_model(d)
+    up, um = O.moyal_tables(m)
+    W = inputs.random_hierarchy(2, 2, 12, 64, seed=870)
+    out = []
+    for use_tables in (False, True):
+        P = qhfpe.Propagator(d, batch=1, precision="fp64")
+        try:
+            if use_tables:
+                P.set_potential_tables(up, um)
+            P.set_tile(4)
+            P.set_state(torch.from_numpy(W[None]))
+            P.apply_rhs()
+            out.append(P.get_state().cpu().numpy()[0])
+        finally:
+            P.close()
+    assert rel(out[1], out[0]) < 1e-13
+    assert rel(out[1], O.rhs(m, W)) < 1e-12
+    P = qhfpe.Propagator(d, batch=1, precision="fp64")
+    try:
+        bad = up.copy()
+        bad[0, 0, 3, 5] = np.nan
+        with pytest.raises(qhfpe.QHFPEError):
+            P.set_potential_tables(bad, um)
+        with pytest.raises(ValueError):
+            P.set_potential_tables(up[:, :, :-1], um)
+    finally:
+        P.close()
