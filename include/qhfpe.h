@@ -126,6 +126,21 @@ int qhfpe_get_phase(const qhfpe_t* h, int32_t* phase);
  * applies.  Synchronous. */
 int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma, double beta);
 
+/* Hierarchy depth of one batch member (Eq. (heom) truncated at its own
+ * level N_b, closed there by Eq. (GMFP)), 0 <= depth <= params.depth; at
+ * create every member has params.depth.  Members of different depths then
+ * share each stage launch: the launch's units run over the levels each
+ * member has, and the levels above a member's depth are neither computed
+ * nor written (qhfpe_init_thermal leaves them zero; a state loaded with
+ * qhfpe_set_state should hold zeros there, since they are carried along
+ * unchanged).  Results of a member equal those of a handle of its own
+ * depth bit for bit.  Not with a learned closure (QHFPE_EUNSUPPORTED).
+ * Synchronous; QHFPE_ESTATE while the handle's stream records a graph;
+ * QHFPE_EINVAL for a member or depth out of range.  With members of
+ * different depths, qhfpe_apply_rhs and qhfpe_residual clear their scratch
+ * state first (and refuse while recording). */
+int qhfpe_set_member_depth(qhfpe_t* h, int32_t member, int32_t depth);
+
 /* Potential surfaces from a host function instead of params.poly (Sec. II,
  * Eq. (system-Hamiltonian); the model of Sec. III has displaced Morse
  * diagonals and a Gaussian coupling, see qhfpe_morse_gauss_potential).

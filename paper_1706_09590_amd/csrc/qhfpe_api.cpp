@@ -43,7 +43,7 @@ struct Layout {
   size_t elem = 0;
   long long member_elems = 0, level_elems = 0, comp_elems = 0;
   size_t state_bytes = 0;
-  size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0;
+  size_t off_y = 0, off_va = 0, off_vb = 0, off_partials = 0, off_red = 0, off_tw = 0, off_flag = 0, off_mlev = 0;
   size_t off_dtab = 0, off_gtab = 0, off_ctab = 0, off_mtab = 0, off_bath = 0, off_psym = 0;
   int n1 = 0, n2 = 0;
   size_t total = 0;
@@ -138,6 +138,9 @@ Layout make_layout(const qhfpe_params* p) {
   off += align_up((size_t)2 * p->np * L.elem);
   L.off_flag = off;
   off += kAlign;
+  // per-member depths: level-row prefix [B + 1] and the member of each row
+  L.off_mlev = off;
+  off += align_up(((size_t)p->batch + 1 + (size_t)p->batch * (p->depth + 1)) * sizeof(int));
   L.total = off;
   return L;
 }
@@ -338,6 +341,11 @@ struct qhfpe_handle {
   // and the closure's W^(N+1) [B][level], in the caller's buffer
   unsigned short* closure_wb = nullptr;
   void* closure_out = nullptr;
+  // per-member hierarchy depths (qhfpe_set_member_depth): mdepth[b] <= depth;
+  // hmlev[b] = sum of the level counts of members before b; mixed when any
+  // member has fewer levels than the handle
+  std::vector<int> mdepth, hmlev;
+  bool mixed = false;
 
   ~qhfpe_handle() {
     for (int g = 0; g < groups_made; ++g) {
@@ -405,6 +413,13 @@ struct qhfpe_handle {
   double* bath() const { return reinterpret_cast<double*>(ws + L.off_bath); }
   void* psym() const { return ws + L.off_psym; }
   int* flag() const { return reinterpret_cast<int*>(ws + L.off_flag); }
+  int* mlev() const { return reinterpret_cast<int*>(ws + L.off_mlev); }
+  int* lev_member() const { return mlev() + p.batch + 1; }
+  // stage units (wave-variant tasks or workgroups) of members first ..
+  // first + count - 1
+  long long units(int first, int count) const {
+    return (long long)ntiles() * (mixed ? hmlev[first + count] - hmlev[first] : (long long)levels * count);
+  }
 
   GridDesc grid() const {
     GridDesc g;
@@ -441,8 +456,11 @@ struct qhfpe_handle {
     a.depth = p.depth;
     a.ntiles = ntiles();
     a.batch = p.batch;
-    a.nblocks_padded = padded_blocks(p.batch);
-    a.wpb = wave_wpb(p.batch);
+    a.mlev = mixed ? mlev() : nullptr;
+    a.lev_member = mixed ? lev_member() : nullptr;
+    a.mfirst = 0;
+    a.nblocks_padded = padded_blocks(0, p.batch);
+    a.wpb = wave_wpb(0, p.batch);
     // the three state arrays of the step against the MI355X's 256 MB
     // memory-side cache: above it, the stage outputs are stored
     // non-temporally (measured: 1024-member 128x128 depth-6 FP32 launch
@@ -466,18 +484,21 @@ struct qhfpe_handle {
     return a;
   }
 
-  // waves per workgroup of a wave-variant launch over `batch` members
-  int wave_wpb(int batch) const {
-    if (ns == 3) return wave3_wpb((int)L.elem, p.np, (long long)ntiles() * levels * batch);
-    return (!qcoup && ntiles() * levels * batch <= kWaveSmallTasks) ? kWaveTasksPerBlockSmall : kWaveTasksPerBlock;
+  // waves per workgroup of a wave-variant launch over members first ..
+  // first + count - 1
+  int wave_wpb(int first, int count) const {
+    const long long tasks = units(first, count);
+    if (ns == 3) return wave3_wpb((int)L.elem, p.np, tasks);
+    return (!qcoup && tasks <= kWaveSmallTasks) ? kWaveTasksPerBlockSmall : kWaveTasksPerBlock;
   }
 
-  // grid of a stage launch over `batch` members, rounded up to a multiple of 8
-  int padded_blocks(int batch) const {
-    const int units = ntiles() * levels * batch;  // workgroups, or waves of the wave variant
-    const int wpb = wave_wpb(batch);
-    const int blocks = wave() ? (units + wpb - 1) / wpb : units;
-    return (blocks + 7) / 8 * 8;
+  // grid of a stage launch over members first .. first + count - 1,
+  // rounded up to a multiple of 8
+  int padded_blocks(int first, int count) const {
+    const long long u = units(first, count);  // workgroups, or waves of the wave variant
+    const int wpb = wave_wpb(first, count);
+    const long long blocks = wave() ? (u + wpb - 1) / wpb : u;
+    return (int)((blocks + 7) / 8 * 8);
   }
 
   // the same stage restricted to members first .. first + count - 1
@@ -490,8 +511,9 @@ struct qhfpe_handle {
     a.bath += (long long)kBathStride * first;
     if (a.partials) a.partials += (long long)first * kRespSlots * a.ntiles;
     a.batch = count;
-    a.nblocks_padded = padded_blocks(count);
-    a.wpb = wave_wpb(count);
+    if (a.mlev) a.mfirst = first;
+    a.nblocks_padded = padded_blocks(first, count);
+    a.wpb = wave_wpb(first, count);
     return a;
   }
 
@@ -653,6 +675,9 @@ int qhfpe_create(const qhfpe_params* params, void* d_workspace, size_t bytes, vo
   h->ns = params->n_states;
   h->nc = h->ns * h->ns;
   h->levels = params->depth + 1;
+  h->mdepth.assign(params->batch, params->depth);
+  h->hmlev.resize(params->batch + 1);
+  for (int b = 0; b <= params->batch; ++b) h->hmlev[b] = b * h->levels;
   h->cpt = tile_default((int)L.elem, params->n_states, params->np);
   h->dq = (params->q_max - params->q_min) / params->nq;
   h->dp = (params->p_max - params->p_min) / params->np;
@@ -757,6 +782,32 @@ int qhfpe_set_member_bath(qhfpe_t* h, int32_t member, double zeta, double gamma,
   HIP_TRY(hipMemcpyAsync(h->bath() + kBathStride * first, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
                          h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return QHFPE_OK;
+}
+
+int qhfpe_set_member_depth(qhfpe_t* h, int32_t member, int32_t depth) {
+  if (int rc = check_handle(h)) return rc;
+  if (member < 0 || member >= h->p.batch) return fail(QHFPE_EINVAL, "member %d out of range", member);
+  if (depth < 0 || depth > h->p.depth) return fail(QHFPE_EINVAL, "depth %d outside 0..%d", depth, h->p.depth);
+  if (h->closure_out && depth != h->p.depth)
+    return fail(QHFPE_EUNSUPPORTED, "a learned closure needs every member at the handle's depth");
+  if (capturing(h)) return fail(QHFPE_ESTATE, "qhfpe_set_member_depth synchronises: not allowed while capturing");
+  std::vector<int> md = h->mdepth;
+  md[member] = depth;
+  std::vector<int> lev(h->p.batch + 1 + (size_t)h->p.batch * h->levels, 0);
+  bool mixed = false;
+  int row = 0;
+  for (int b = 0; b < h->p.batch; ++b) {
+    lev[b] = row;
+    for (int n = 0; n <= md[b]; ++n) lev[h->p.batch + 1 + row++] = b;
+    mixed = mixed || md[b] != h->p.depth;
+  }
+  lev[h->p.batch] = row;
+  HIP_TRY(hipMemcpyAsync(h->mlev(), lev.data(), lev.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->mdepth = md;
+  h->hmlev.assign(lev.begin(), lev.begin() + h->p.batch + 1);
+  h->mixed = mixed;
   return QHFPE_OK;
 }
 
@@ -1063,8 +1114,18 @@ int qhfpe_response(qhfpe_t* h, double* d_out) {
   return finalize(h, 1, d_out, 2, 0);
 }
 
+// With per-member depths a stage leaves the levels above a member's depth
+// unwritten: clear the output buffer first where it is read as a whole.
+static int clear_for_whole_read(qhfpe_t* h, void* buf) {
+  if (!h->mixed) return QHFPE_OK;
+  if (capturing(h)) return fail(QHFPE_ESTATE, "not while recording with per-member depths");
+  HIP_TRY(hipMemsetAsync(buf, 0, (size_t)h->L.member_elems * h->p.batch * h->L.elem, h->stream));
+  return QHFPE_OK;
+}
+
 int qhfpe_apply_rhs(qhfpe_t* h) {
   if (int rc = check_handle(h)) return rc;
+  if (int rc = clear_for_whole_read(h, h->va())) return rc;
   StageArgs a = h->stage_args(h->y(), nullptr, h->va(), 1.0);
   HIP_TRY(h->launch(a));
   HIP_TRY(hipMemcpyAsync(h->y(), h->va(), (size_t)h->L.member_elems * h->p.batch * h->L.elem,
@@ -1075,6 +1136,7 @@ int qhfpe_apply_rhs(qhfpe_t* h) {
 int qhfpe_residual(qhfpe_t* h, double* h_out) {
   if (int rc = check_handle(h)) return rc;
   if (!h_out) return fail(QHFPE_EINVAL, "h_out is NULL");
+  if (int rc = clear_for_whole_read(h, h->va())) return rc;
   StageArgs a = h->stage_args(h->y(), nullptr, h->va(), 1.0);
   HIP_TRY(h->launch(a));
   std::vector<double> nl, nw;
@@ -1178,6 +1240,7 @@ int qhfpe_set_closure(qhfpe_t* h, const float* d_kernel, void* d_buffer, size_t 
   }
   if (!wave_supported(h->ns, h->p.np))
     return fail(QHFPE_EUNSUPPORTED, "a learned closure needs two states and np = 128 or 256");
+  if (h->mixed) return fail(QHFPE_EUNSUPPORTED, "a learned closure needs every member at the handle's depth");
   if (!d_buffer || reinterpret_cast<uintptr_t>(d_buffer) % kAlign)
     return fail(QHFPE_EINVAL, "d_buffer must be a 256-byte aligned device buffer");
   size_t need = 0;

@@ -106,6 +106,13 @@ struct StageArgs {
   const double* bath;    // [B][kBathStride]: r0/m (= zeta), gamma, c0, c_delta, beta per member
   const void* psym;      // [2][np]: DFT symbols of D_p2 and D_p D_p, divided by np
   const void* closure;   // wave variant: learned W^(N+1) [B][4][nq][np] (one level per member), or nullptr
+  // per-member depths (nullptr: every member has `depth`): member b has
+  // levels mlev[b] .. mlev[b + 1] - 1 of a row numbering over all members,
+  // and lev_member[row] is the member of a row.  mfirst: the member (in
+  // that numbering) of this launch's member 0.
+  const int* mlev;
+  const int* lev_member;
+  int mfirst;
   int slot;
   int qcoup;  // 1: q-dependent coupling through the r-space multiply (wave variant, two states)
   int nq;

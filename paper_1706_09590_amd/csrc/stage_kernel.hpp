@@ -142,6 +142,37 @@ __device__ __forceinline__ cx<T> coupling_rspace(const cx<T> (&H)[NS][NS], const
   return {s.im, -s.re};
 }
 
+// Position of stage unit t of a launch (a task of the wave variants, a
+// workgroup of this one): levels fastest, then q tiles, then members.  With
+// per-member depths (StageArgs::mlev) member b owns ntiles * (its levels)
+// consecutive units, and every row of ntiles units belongs to one member.
+struct UnitPos {
+  int b, tile, n, depth;
+};
+__device__ __forceinline__ int stage_units(const StageArgs& a) {
+  return a.mlev ? a.ntiles * (a.mlev[a.mfirst + a.batch] - a.mlev[a.mfirst]) : a.ntiles * (a.depth + 1) * a.batch;
+}
+__device__ __forceinline__ UnitPos unit_pos(const StageArgs& a, int t) {
+  UnitPos u;
+  if (a.mlev == nullptr) {
+    const int L = a.depth + 1;
+    u.n = t % L;
+    u.tile = (t / L) % a.ntiles;
+    u.b = t / (L * a.ntiles);
+    u.depth = a.depth;
+    return u;
+  }
+  const int tg = t + a.ntiles * a.mlev[a.mfirst];
+  const int bg = a.lev_member[tg / a.ntiles];
+  const int r0 = a.mlev[bg], L = a.mlev[bg + 1] - r0;
+  const int local = tg - a.ntiles * r0;
+  u.n = local % L;
+  u.tile = local / L;
+  u.b = bg - a.mfirst;
+  u.depth = L - 1;
+  return u;
+}
+
 template <typename T, int NS, int NP, int CPT_, bool QC = false>
 __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel(StageArgs a) {
   using P = PlanOf<T, NS, NP, CPT_>;
@@ -165,18 +196,15 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   __shared__ cx<T> stw[N1 * (N2 + 1)];  // w^(n2 k1), row k1 padded to N2 + 1
   __shared__ T ssym[2 * NP];            // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
 
-  const int nblocks = a.ntiles * (a.depth + 1) * a.batch;
+  const int nblocks = stage_units(a);
   const int lb = xcd_logical_block(blockIdx.x, a.nblocks_padded);
   if (lb >= nblocks) return;
   const int tid = threadIdx.x;
   // levels run fastest: the blocks of every level of one q tile are
   // resident together, so the reads of v^(n) by levels n - 1 and n + 1
   // hit the copy that level n's own block brought into L2
-  const int L = a.depth + 1;
-  const int n = lb % L;
-  const int rest = lb / L;
-  const int tile = rest % a.ntiles;
-  const int b = rest / a.ntiles;
+  const UnitPos pos = unit_pos(a, lb);
+  const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = tile * TQ;
   const int nq = a.nq;
   const int ia = tid % NP;           // this thread's p node
@@ -189,7 +217,7 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   constexpr unsigned ES = sizeof(T);
   const unsigned level_bytes = (unsigned)(a.level_stride * ES);
   const T* vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
-  const bool has_up = n < a.depth, has_dn = n >= 1;
+  const bool has_up = n < pos.depth, has_dn = n >= 1;
   const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);
   const rsrc_t ru = make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, level_bytes);
   const rsrc_t rd = make_rsrc(vm + (long long)(has_dn ? n - 1 : n) * a.level_stride, level_bytes);

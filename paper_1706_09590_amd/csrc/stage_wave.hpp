@@ -102,9 +102,7 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   // scalar registers instead of per-lane loops over descriptor values
   const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nq = a.nq;
-  const int ntiles = a.ntiles;  // tasks per level = groups of C columns
-  const int L = a.depth + 1;
-  const int ntasks = ntiles * L * a.batch;
+  const int ntasks = stage_units(a);
   // levels fastest, as in stage_kernel: the tasks of all levels of one
   // column group run together and share their level neighbours through L2
   const int task_id = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
@@ -112,9 +110,8 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   // barrier below; it takes task 0's indices and ends after the barrier
   const bool active = task_id < ntasks;
   const int task = active ? task_id : 0;
-  const int n = task % L;
-  const int tile = (task / L) % ntiles;
-  const int b = task / (L * ntiles);
+  const UnitPos pos = unit_pos(a, task);
+  const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = C * tile;
   T* const s = sbuf[wid];
 
@@ -125,7 +122,7 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   // Loads past a descriptor's size return zero.  That supplies the zero
   // ghost columns beyond the q edges (their offsets are set past every
   // level), v^(n+1) at n = N, v^(n-1) at n = 0 and a missing y.
-  const bool has_up = n < a.depth, has_dn = n >= 1;
+  const bool has_up = n < pos.depth, has_dn = n >= 1;
   // learned terminator: at n = N the level above is the closure's W^(N+1)
   const bool clos = a.closure != nullptr && !has_up;
   const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);

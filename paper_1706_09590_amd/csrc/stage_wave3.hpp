@@ -84,9 +84,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nq = a.nq;
-  const int ntiles = a.ntiles;  // tasks per level = pairs of q columns
-  const int L = a.depth + 1;
-  const int ntasks = ntiles * L * a.batch;
+  const int ntasks = stage_units(a);
   // levels fastest, so that the tasks of all levels of one column pair run
   // together and share their level neighbours through L2
   const int task_id = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
@@ -94,9 +92,8 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   // barrier below; it takes task 0's indices and ends after the barrier
   const bool active = task_id < ntasks;
   const int task = active ? task_id : 0;
-  const int n = task % L;
-  const int tile = (task / L) % ntiles;
-  const int b = task / (L * ntiles);
+  const UnitPos pos = unit_pos(a, task);
+  const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = C * tile;
   T* const s = sbuf[wid];
 
@@ -106,7 +103,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   const T* vm = static_cast<const T*>(a.v) + (long long)b * a.member_stride;
   // loads past a descriptor's size return zero: the ghost columns beyond
   // the q edges, v^(n+1) at n = N, v^(n-1) at n = 0 and a missing y
-  const bool has_up = n < a.depth, has_dn = n >= 1;
+  const bool has_up = n < pos.depth, has_dn = n >= 1;
   const rsrc_t rn = make_rsrc(vm + (long long)n * a.level_stride, level_bytes);
   const rsrc_t ru = make_rsrc(vm + (long long)(has_up ? n + 1 : n) * a.level_stride, has_up ? level_bytes : 0u);
   const rsrc_t rd = make_rsrc(vm + (long long)(has_dn ? n - 1 : n) * a.level_stride, has_dn ? level_bytes : 0u);

@@ -81,6 +81,7 @@ def lib():
         "qhfpe_get_state": ([_vp, _vp, _c_i32], _c_int),
         "qhfpe_get_phase": ([_vp, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_set_member_bath": ([_vp, _c_i32, _c_dbl, _c_dbl, _c_dbl], _c_int),
+        "qhfpe_set_member_depth": ([_vp, _c_i32, _c_i32], _c_int),
         "qhfpe_set_tile": ([_vp, _c_i32], _c_int),
         "qhfpe_autotune": ([_vp, _c_i32, ctypes.POINTER(_c_i32)], _c_int),
         "qhfpe_set_streams": ([_vp, _c_i32], _c_int),
@@ -246,6 +247,11 @@ class Propagator:
 
     def set_member_bath(self, member: int, zeta: float, gamma: float, beta: float):
         _check(lib().qhfpe_set_member_bath(self.handle, int(member), float(zeta), float(gamma), float(beta)))
+
+    def set_member_depth(self, member: int, depth: int):
+        """Hierarchy depth of one member (<= the model's depth;
+        qhfpe_set_member_depth)."""
+        _check(lib().qhfpe_set_member_depth(self.handle, int(member), int(depth)))
 
     def set_tile(self, cells_per_thread: int):
         _check(lib().qhfpe_set_tile(self.handle, int(cells_per_thread)))

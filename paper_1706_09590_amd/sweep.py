@@ -104,8 +104,13 @@ def substeps_for(dt: float, rho, margin: float = RK4_MARGIN):
     return np.maximum(1, np.ceil(dt * np.asarray(rho) / margin)).astype(int)
 
 
-def plan(members, dt: float, estimate_iters: int = 40, device=None):
-    """Substeps per member and the batches: list of (model, [member ids], substeps)."""
+def plan(members, dt: float, estimate_iters: int = 40, device=None, merge_depths: bool = True):
+    """Substeps per member and the batches: list of (model, [member ids], substeps).
+
+    The substeps come from each member's own operator (its grid and depth).
+    merge_depths: members that differ only in their hierarchy depth share a
+    batch (the model has the largest depth; run_sweep gives every member its
+    own, qhfpe_set_member_depth), so that they share every stage launch."""
     by_shape = {}
     for i, m in enumerate(members):
         mod = member_model(m, dt)
@@ -115,17 +120,34 @@ def plan(members, dt: float, estimate_iters: int = 40, device=None):
         rho = spectral_radius(mod, [(members[i]["zeta"], members[i]["gamma"], members[i]["beta"]) for i in ids],
                               iters=estimate_iters, device=device)
         subs[ids] = substeps_for(dt, rho)
-    batches = []
+    groups = {}
     for mod, ids in by_shape.values():
         for s in sorted(set(subs[ids].tolist())):
-            batches.append((mod, [i for i in ids if subs[i] == s], int(s)))
+            key = _shape_key(mod)
+            key = (key[:3] + key[4:] if merge_depths else key, int(s))
+            deepest, grouped = groups.setdefault(key, (mod, []))
+            grouped.extend(i for i in ids if subs[i] == s)
+            if mod["depth"] > deepest["depth"]:
+                groups[key] = (mod, grouped)
+    batches = [(mod, sorted(ids), s) for (_, s), (mod, ids) in groups.items()]
     return subs, batches
 
 
-def batch_reals(batch) -> int:
-    """Packed reals of a batch's state (all members and levels)."""
+def member_depths(batch, members=None):
+    """Each member's hierarchy depth in a batch (the model's when members is
+    None or a member has no depth of its own)."""
     mod, ids, _ = batch
-    return (mod["depth"] + 1) * mod["nq"] * mod["np"] * mod["n_states"] ** 2 * len(ids)
+    if members is None:
+        return [mod["depth"]] * len(ids)
+    return [int(members[i].get("depth", mod["depth"])) for i in ids]
+
+
+def batch_reals(batch, members=None) -> int:
+    """Packed reals that a batch's stages compute (the levels of every
+    member, each at its own depth when members is given)."""
+    mod, ids, _ = batch
+    levels = sum(d + 1 for d in member_depths(batch, members))
+    return levels * mod["nq"] * mod["np"] * mod["n_states"] ** 2
 
 
 def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams: int = 1, batches=None,
@@ -158,6 +180,7 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
 
     def run_batch(job):
         mod, ids, subs = job
+        depths = member_depths(job, members)
         t_start = time.perf_counter()
         s = torch.cuda.Stream(device=dev)
         with torch.cuda.stream(s):
@@ -167,6 +190,8 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 for j, i in enumerate(ids):
                     m = members[i]
                     P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
+                    if depths[j] != mod["depth"]:
+                        P.set_member_depth(j, depths[j])
                 t_made = time.perf_counter()
                 P.autotune(5)  # the fastest stage variant for this batch's shape and size
                 t_tuned = time.perf_counter()
@@ -186,24 +211,25 @@ def run_sweep(members, nsteps: int, dt: float, precision: str = "fp32", streams:
                 R1 = ((1j / mod.get("hbar", 1.0)) * tr).cpu().numpy()
             finally:
                 P.close()
-        cells = (mod["depth"] + 1) * mod["nq"] * mod["np"]
+        cells = sum(d + 1 for d in depths) * mod["nq"] * mod["np"]
         with lock:
             for j, i in enumerate(ids):
                 results[i] = R1[j]
                 growth[i] = n_end[j] / max(n_mid[j], 1e-300)
-            counts["cell_updates"] += cells * len(ids) * nsteps * subs
-            timings.append(dict(grid=mod["nq"], depth=mod["depth"], n_states=mod["n_states"], members=len(ids),
+            counts["cell_updates"] += cells * nsteps * subs
+            timings.append(dict(grid=mod["nq"], depth=mod["depth"], member_depths=sorted(set(depths)),
+                                n_states=mod["n_states"], members=len(ids),
                                 substeps=subs, seconds=time.perf_counter() - t_start,
                                 setup_s=t_made - t_start, tune_s=t_tuned - t_made,
                                 gpu_s=ev0.elapsed_time(ev1) * 1e-3,
-                                cell_updates=cells * len(ids) * nsteps * subs))
+                                cell_updates=cells * nsteps * subs))
         return len(ids)
 
     # largest batches first, so that the small ones fill in at the end
-    order = sorted(batches, key=lambda b: -(b[0]["depth"] + 1) * b[0]["nq"] * b[0]["np"] * len(b[1]) * b[2])
+    order = sorted(batches, key=lambda b: -batch_reals(b, members) // b[0]["n_states"] ** 2 * b[2])
     if small_streams > 0:
-        large = [b for b in order if batch_reals(b) >= small_reals]
-        small = [b for b in order if batch_reals(b) < small_reals]
+        large = [b for b in order if batch_reals(b, members) >= small_reals]
+        small = [b for b in order if batch_reals(b, members) < small_reals]
     else:
         large, small = order, []
     with ThreadPoolExecutor(max_workers=max(1, int(streams))) as ex:
@@ -229,16 +255,24 @@ def amplification(members, nsteps: int, dt: float, batches=None, seed: int = 11,
     if batches is None:
         _, batches = plan(members, dt, device=device)
     amp = np.zeros(len(members))
-    for mod, ids, subs in batches:
+    for batch in batches:
+        mod, ids, subs = batch
+        depths = member_depths(batch, members)
         P = qhfpe.Propagator(inputs.model_dict(mod, dt=dt / subs), batch=len(ids), precision=precision,
                              device=device)
         try:
+            # each member starts from the seeded hierarchy of its own depth
+            # (zero above it)
+            ns = mod["n_states"]
+            S = np.zeros((len(ids), mod["depth"] + 1, ns, ns, mod["nq"], mod["np"]), dtype=np.complex128)
             for j, i in enumerate(ids):
                 m = members[i]
                 P.set_member_bath(j, m["zeta"], m["gamma"], m["beta"])
-            W = inputs.random_hierarchy(mod["depth"], mod["n_states"], mod["nq"], mod["np"], seed=seed,
-                                        smooth=False)
-            P.set_state(torch.from_numpy(np.broadcast_to(W, (len(ids),) + W.shape).copy()), phase=0)
+                if depths[j] != mod["depth"]:
+                    P.set_member_depth(j, depths[j])
+                S[j, :depths[j] + 1] = inputs.random_hierarchy(depths[j], mod["n_states"], mod["nq"], mod["np"],
+                                                               seed=seed, smooth=False)
+            P.set_state(torch.from_numpy(S), phase=0)
             P.step(nsteps * subs, 1, record=False)
             n1 = P.residual()[:, 1]
             P.step(nsteps * subs, 1, record=False)
@@ -253,5 +287,6 @@ def sweep_cell_updates(members, nsteps: int, substeps) -> int:
     return int(sum((m["depth"] + 1) * m["grid"] ** 2 * nsteps * int(s) for m, s in zip(members, substeps)))
 
 
-__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "batch_reals", "run_sweep", "amplification",
+__all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "member_depths", "batch_reals", "run_sweep",
+           "amplification",
            "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG", "SMALL_REALS", "SMALL_STREAMS"]

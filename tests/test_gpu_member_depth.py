@@ -1,0 +1,152 @@
+"""Members of one batch with hierarchy depths of their own
+(qhfpe_set_member_depth): each member equals a handle of its own depth bit
+for bit (every stage variant, both precisions, member groups), and the
+operator of a mixed batch equals the oracle's per member (Eq. (heom) closed
+by Eq. (GMFP) at the member's own depth).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import oracle_model
+from oracle import qhfpe_oracle as O
+from paper_1706_09590_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1706_09590_amd import qhfpe  # noqa: E402
+
+BATHS = [(0.5, 1.0, 1.0), (1.0, 0.8, 0.7), (0.3, 1.2, 1.5), (0.8, 1.0, 0.9), (0.6, 0.9, 1.1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+def model(ns, np_, nq, depth):
+    base = inputs.SMALL_ABSORPTION["model"]
+    if ns == 2:
+        return inputs.model_dict(base, nq=nq, np=np_, depth=depth)
+    return inputs.model_dict(base, n_states=3, nq=nq, np=np_, depth=depth, poly=inputs.three_state_surfaces(0.3, 0.2),
+                             mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])
+
+
+def run(d, precision, tile, depths, groups=1, nsteps=8, stride=2):
+    P = qhfpe.Propagator(d, batch=len(depths), precision=precision)
+    try:
+        for b, dep in enumerate(depths):
+            P.set_member_bath(b, *BATHS[b])
+            if dep != d["depth"]:
+                P.set_member_depth(b, dep)
+        P.set_tile(tile)
+        P.set_streams(groups)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        tr = P.step(nsteps, stride).cpu().numpy()
+        return tr, P.get_state().cpu().numpy()
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("ns,np_,nq,precision,tile", [
+    (2, 128, 20, "fp64", 1), (2, 256, 12, "fp32", 1), (3, 128, 14, "fp64", 1), (3, 256, 10, "fp32", 1),
+    (2, 64, 13, "fp64", 4), (3, 48, 11, "fp64", 2)])
+def test_each_member_equals_a_handle_of_its_own_depth(ns, np_, nq, precision, tile):
+    say(f"member depths ns={ns} np={np_} {precision} tile={tile}")
+    N = 4
+    depths = [N, 2, 0]
+    tr, st = run(model(ns, np_, nq, N), precision, tile, depths)
+    for b, dep in enumerate(depths):
+        P = qhfpe.Propagator(model(ns, np_, nq, dep), batch=1, precision=precision)
+        try:
+            P.set_member_bath(0, *BATHS[b])
+            P.set_tile(tile)
+            P.init_thermal(1.0)
+            P.apply_dipole()
+            tr1 = P.step(8, 2).cpu().numpy()
+            st1 = P.get_state().cpu().numpy()
+        finally:
+            P.close()
+        np.testing.assert_array_equal(tr[b], tr1[0])
+        np.testing.assert_array_equal(st[b, :dep + 1], st1[0])
+        assert not np.any(st[b, dep + 1:])
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_member_groups_with_mixed_depths_are_bitwise(tile):
+    """Five members of depths 5, 0, 3, 5, 1 in one launch and in two member
+    groups (each group's launch starts at another member of the row table)."""
+    say(f"member depths and groups tile={tile}")
+    d = model(2, 128, 16, 5)
+    depths = [5, 0, 3, 5, 1]
+    a = run(d, "fp64", tile, depths, groups=1)
+    b = run(d, "fp64", tile, depths, groups=2)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("ns,np_,tile", [(2, 128, 1), (3, 128, 1), (2, 96, 4)])
+def test_mixed_batch_operator_matches_the_oracle(ns, np_, tile):
+    """qhfpe_apply_rhs on a batch of members of depths 3, 1, 0 against the
+    oracle's operator of each member at its own depth."""
+    say(f"mixed-depth rhs ns={ns} np={np_} tile={tile}")
+    N, nq = 3, 13
+    depths = [3, 1, 0]
+    d = model(ns, np_, nq, N)
+    S = np.zeros((3, N + 1, ns, ns, nq, np_), dtype=np.complex128)
+    for b, dep in enumerate(depths):
+        S[b, :dep + 1] = inputs.random_hierarchy(dep, ns, nq, np_, seed=900 + b)
+    P = qhfpe.Propagator(d, batch=3, precision="fp64")
+    try:
+        for b, dep in enumerate(depths):
+            P.set_member_bath(b, *BATHS[b])
+            if dep != N:
+                P.set_member_depth(b, dep)
+        P.set_tile(tile)
+        P.set_state(torch.from_numpy(S))
+        r = P.residual()
+        P.apply_rhs()
+        got = P.get_state().cpu().numpy()
+    finally:
+        P.close()
+    for b, dep in enumerate(depths):
+        m = oracle_model(inputs.model_dict(d, depth=dep, zeta=BATHS[b][0], gamma=BATHS[b][1], beta=BATHS[b][2]))
+        ref = O.rhs(m, S[b, :dep + 1])
+        assert rel(got[b, :dep + 1], ref) < 1e-12, b
+        assert not np.any(got[b, dep + 1:])
+        # qhfpe_residual's norms (||L W||, ||W||) equal those of the member alone
+        Q = qhfpe.Propagator(inputs.model_dict(d, depth=dep), batch=1, precision="fp64")
+        try:
+            Q.set_member_bath(0, *BATHS[b])
+            Q.set_tile(tile)
+            Q.set_state(torch.from_numpy(S[b:b + 1, :dep + 1].copy()))
+            r1 = Q.residual()
+        finally:
+            Q.close()
+        assert r[b] == pytest.approx(r1[0], rel=1e-12), b
+
+
+def test_member_depth_arguments():
+    d = model(2, 128, 16, 3)
+    P = qhfpe.Propagator(d, batch=2, precision="fp64")
+    try:
+        for member, depth in ((2, 1), (-1, 1), (0, 4), (0, -1)):
+            with pytest.raises(qhfpe.QHFPEError) as e:
+                P.set_member_depth(member, depth)
+            assert e.value.code == qhfpe.EINVAL
+        P.set_member_depth(1, 0)
+        P.set_member_depth(1, 3)  # back to the handle's depth
+    finally:
+        P.close()
