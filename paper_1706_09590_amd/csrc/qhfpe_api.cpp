@@ -466,8 +466,11 @@ struct qhfpe_handle {
     // non-temporally (measured: 1024-member 128x128 depth-6 FP32 launch
     // 1248 -> 1201 us; at 113 MB, two 256x256 depth-8 FP64 members, the
     // same stores cost 17%)
+    // (the levels the stages touch: with per-member depths, fewer than the
+    // handle holds)
     constexpr double kMemorySideCacheBytes = 256.0 * 1024 * 1024;
-    a.stream_out = 3.0 * (double)L.member_elems * p.batch * L.elem > kMemorySideCacheBytes ? 1 : 0;
+    const double touched = (double)(mixed ? hmlev[p.batch] : (long long)levels * p.batch) * L.level_elems;
+    a.stream_out = 3.0 * touched * L.elem > kMemorySideCacheBytes ? 1 : 0;
     a.member_stride = L.member_elems;
     a.level_stride = L.level_elems;
     a.comp_stride = L.comp_elems;

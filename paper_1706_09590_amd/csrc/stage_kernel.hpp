@@ -143,18 +143,23 @@ __device__ __forceinline__ cx<T> coupling_rspace(const cx<T> (&H)[NS][NS], const
 }
 
 // Position of stage unit t of a launch (a task of the wave variants, a
-// workgroup of this one): levels fastest, then q tiles, then members.  With
-// per-member depths (StageArgs::mlev) member b owns ntiles * (its levels)
-// consecutive units, and every row of ntiles units belongs to one member.
+// workgroup of this one): levels fastest, then q tiles, then members.  MIX:
+// members have depths of their own (StageArgs::mlev): member b owns
+// ntiles * (its levels) consecutive units, and every row of ntiles units
+// belongs to one member.  (A compile-time switch: the lookup's dependent
+// scalar loads would otherwise lengthen every wave's start.)
 struct UnitPos {
   int b, tile, n, depth;
 };
+template <bool MIX>
 __device__ __forceinline__ int stage_units(const StageArgs& a) {
-  return a.mlev ? a.ntiles * (a.mlev[a.mfirst + a.batch] - a.mlev[a.mfirst]) : a.ntiles * (a.depth + 1) * a.batch;
+  if constexpr (MIX) return a.ntiles * (a.mlev[a.mfirst + a.batch] - a.mlev[a.mfirst]);
+  return a.ntiles * (a.depth + 1) * a.batch;
 }
+template <bool MIX>
 __device__ __forceinline__ UnitPos unit_pos(const StageArgs& a, int t) {
   UnitPos u;
-  if (a.mlev == nullptr) {
+  if constexpr (!MIX) {
     const int L = a.depth + 1;
     u.n = t % L;
     u.tile = (t / L) % a.ntiles;
@@ -173,7 +178,7 @@ __device__ __forceinline__ UnitPos unit_pos(const StageArgs& a, int t) {
   return u;
 }
 
-template <typename T, int NS, int NP, int CPT_, bool QC = false>
+template <typename T, int NS, int NP, int CPT_, bool QC = false, bool MIX = false>
 __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel(StageArgs a) {
   using P = PlanOf<T, NS, NP, CPT_>;
   constexpr int N1 = P::N1, N2 = P::N2, TQ = P::TQ, NT = P::NT, CPT = P::CPT;
@@ -196,14 +201,14 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
   __shared__ cx<T> stw[N1 * (N2 + 1)];  // w^(n2 k1), row k1 padded to N2 + 1
   __shared__ T ssym[2 * NP];            // DFT symbols of D_p2 and D_p D_p (scaled by 1/np)
 
-  const int nblocks = stage_units(a);
+  const int nblocks = stage_units<MIX>(a);
   const int lb = xcd_logical_block(blockIdx.x, a.nblocks_padded);
   if (lb >= nblocks) return;
   const int tid = threadIdx.x;
   // levels run fastest: the blocks of every level of one q tile are
   // resident together, so the reads of v^(n) by levels n - 1 and n + 1
   // hit the copy that level n's own block brought into L2
-  const UnitPos pos = unit_pos(a, lb);
+  const UnitPos pos = unit_pos<MIX>(a, lb);
   const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = tile * TQ;
   const int nq = a.nq;
@@ -662,7 +667,12 @@ __global__ void __launch_bounds__((PlanOf<T, NS, NP, CPT_>::NT), 2) stage_kernel
 template <typename T, int NS, int NP, int CPT, bool QC = false>
 hipError_t launch_stage_variant(const StageArgs& a, int nblocks, hipStream_t s) {
   if constexpr (cpt_supported_c((int)sizeof(T), NS, CPT)) {
-    hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT, QC>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0, s, a);
+    if (a.mlev)
+      hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT, QC, true>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((stage_kernel<T, NS, NP, CPT, QC, false>), dim3(nblocks), dim3(PlanOf<T, NS, NP, CPT>::NT), 0,
+                         s, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

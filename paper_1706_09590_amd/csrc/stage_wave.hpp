@@ -83,8 +83,9 @@ __device__ __forceinline__ void buf_store_n(const double* v, rsrc_t r, unsigned 
 // of LDS per four-wave workgroup allows no more).
 // NTS: non-temporal output stores (the launcher picks it when the state
 // arrays exceed the memory-side cache, StageArgs::stream_out).  WPB: waves
-// per workgroup (StageArgs::wpb).
-template <typename T, int NP, bool QC, bool NTS = false, int WPB_ = kWaveTasksPerBlock>
+// per workgroup (StageArgs::wpb).  MIX: members of their own depths
+// (StageArgs::mlev).
+template <typename T, int NP, bool QC, bool NTS = false, int WPB_ = kWaveTasksPerBlock, bool MIX = false>
 __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !QC ? 4 : 2))
     stage_wave_kernel(StageArgs a) {
   using W = WavePlan<NP, WPB_>;
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   // scalar registers instead of per-lane loops over descriptor values
   const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nq = a.nq;
-  const int ntasks = stage_units(a);
+  const int ntasks = stage_units<MIX>(a);
   // levels fastest, as in stage_kernel: the tasks of all levels of one
   // column group run together and share their level neighbours through L2
   const int task_id = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   // barrier below; it takes task 0's indices and ends after the barrier
   const bool active = task_id < ntasks;
   const int task = active ? task_id : 0;
-  const UnitPos pos = unit_pos(a, task);
+  const UnitPos pos = unit_pos<MIX>(a, task);
   const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = C * tile;
   T* const s = sbuf[wid];
@@ -579,9 +580,15 @@ __global__ void __launch_bounds__((WavePlan<NP, WPB_>::NT), (sizeof(T) == 4 && !
   }
 }
 
+// (MIX: members of their own depths, StageArgs::mlev)
 template <typename T, int NP, bool QC, bool NTS, int WPB>
 hipError_t launch_wave_one(const StageArgs& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((stage_wave_kernel<T, NP, QC, NTS, WPB>), dim3(nblocks), dim3(WavePlan<NP, WPB>::NT), 0, s, a);
+  if (a.mlev)
+    hipLaunchKernelGGL((stage_wave_kernel<T, NP, QC, NTS, WPB, true>), dim3(nblocks), dim3(WavePlan<NP, WPB>::NT), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((stage_wave_kernel<T, NP, QC, NTS, WPB, false>), dim3(nblocks), dim3(WavePlan<NP, WPB>::NT), 0,
+                       s, a);
   return hipGetLastError();
 }
 

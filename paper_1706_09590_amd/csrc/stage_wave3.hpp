@@ -68,8 +68,9 @@ constexpr int wave3_waves_per_simd() {
 }
 
 // NTS: non-temporal output stores (StageArgs::stream_out).  WPB: waves per
-// workgroup (StageArgs::wpb).
-template <typename T, int NP, bool NTS, int WPB_>
+// workgroup (StageArgs::wpb).  MIX: members of their own depths
+// (StageArgs::mlev).
+template <typename T, int NP, bool NTS, int WPB_, bool MIX>
 __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_simd<T, NP>()))
     stage_wave3_kernel(StageArgs a) {
   using W = WavePlan3<NP, WPB_>;
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nq = a.nq;
-  const int ntasks = stage_units(a);
+  const int ntasks = stage_units<MIX>(a);
   // levels fastest, so that the tasks of all levels of one column pair run
   // together and share their level neighbours through L2
   const int task_id = xcd_logical_block(blockIdx.x, a.nblocks_padded) * WPB + wid;
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   // barrier below; it takes task 0's indices and ends after the barrier
   const bool active = task_id < ntasks;
   const int task = active ? task_id : 0;
-  const UnitPos pos = unit_pos(a, task);
+  const UnitPos pos = unit_pos<MIX>(a, task);
   const int n = pos.n, tile = pos.tile, b = pos.b;
   const int q0 = C * tile;
   T* const s = sbuf[wid];
@@ -487,9 +488,15 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   }
 }
 
+// (MIX: members of their own depths, StageArgs::mlev)
 template <typename T, int NP, bool NTS, int WPB>
 hipError_t launch_wave3_one(const StageArgs& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((stage_wave3_kernel<T, NP, NTS, WPB>), dim3(nblocks), dim3(WavePlan3<NP, WPB>::NT), 0, s, a);
+  if (a.mlev)
+    hipLaunchKernelGGL((stage_wave3_kernel<T, NP, NTS, WPB, true>), dim3(nblocks), dim3(WavePlan3<NP, WPB>::NT), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((stage_wave3_kernel<T, NP, NTS, WPB, false>), dim3(nblocks), dim3(WavePlan3<NP, WPB>::NT), 0, s,
+                       a);
   return hipGetLastError();
 }
 

@@ -47,6 +47,10 @@ RK4_MARGIN = 2.0  # dt * rho allowed per substep (RK4 is stable to about 2.8)
 GROWTH_FLAG = 2.0  # ||W(T)|| / ||W(T/2)|| above this marks a growing member
 SMALL_REALS = 8_000_000  # batches below this many packed reals leave most of the GPU idle
 SMALL_STREAMS = 8  # small batches run this many at a time
+# largest batch of merged depths: its three FP32 state arrays stay within the
+# MI355X's 256 MiB memory-side cache (stage passes of batches that fit run
+# about 1.25x faster than of those that do not)
+BATCH_REALS_CAP = 21_000_000
 
 
 def member_model(member: dict, dt: float) -> dict:
@@ -108,9 +112,11 @@ def plan(members, dt: float, estimate_iters: int = 40, device=None, merge_depths
     """Substeps per member and the batches: list of (model, [member ids], substeps).
 
     The substeps come from each member's own operator (its grid and depth).
-    merge_depths: members that differ only in their hierarchy depth share a
-    batch (the model has the largest depth; run_sweep gives every member its
-    own, qhfpe_set_member_depth), so that they share every stage launch."""
+    merge_depths: members that differ only in their hierarchy depth share
+    batches (the model has the largest depth of its batch; run_sweep gives
+    every member its own, qhfpe_set_member_depth), so that they share every
+    stage launch: as few batches per shape as BATCH_REALS_CAP packed reals
+    allow, filled evenly."""
     by_shape = {}
     for i, m in enumerate(members):
         mod = member_model(m, dt)
@@ -120,16 +126,40 @@ def plan(members, dt: float, estimate_iters: int = 40, device=None, merge_depths
         rho = spectral_radius(mod, [(members[i]["zeta"], members[i]["gamma"], members[i]["beta"]) for i in ids],
                               iters=estimate_iters, device=device)
         subs[ids] = substeps_for(dt, rho)
+    if not merge_depths:
+        batches = []
+        for mod, ids in by_shape.values():
+            for s in sorted(set(subs[ids].tolist())):
+                batches.append((mod, [i for i in ids if subs[i] == s], int(s)))
+        return subs, batches
     groups = {}
     for mod, ids in by_shape.values():
         for s in sorted(set(subs[ids].tolist())):
             key = _shape_key(mod)
-            key = (key[:3] + key[4:] if merge_depths else key, int(s))
-            deepest, grouped = groups.setdefault(key, (mod, []))
-            grouped.extend(i for i in ids if subs[i] == s)
-            if mod["depth"] > deepest["depth"]:
-                groups[key] = (mod, grouped)
-    batches = [(mod, sorted(ids), s) for (_, s), (mod, ids) in groups.items()]
+            groups.setdefault((key[:3] + key[4:], int(s)), []).extend(
+                (mod, i) for i in ids if subs[i] == s)
+    def reals(mod):
+        return (mod["depth"] + 1) * mod["nq"] * mod["np"] * mod["n_states"] ** 2
+
+    batches = []
+    for (_, s), entries in groups.items():
+        # as few batches as the cap allows, balanced: deepest member first,
+        # each into the least-filled batch that has room for it
+        entries.sort(key=lambda e: (-e[0]["depth"], e[1]))
+        k = max(1, -(-sum(reals(m) for m, _ in entries) // BATCH_REALS_CAP))
+        bins, loads = [[] for _ in range(k)], [0] * k
+        for mod, i in entries:
+            j = min(range(len(bins)), key=lambda x: loads[x])
+            if loads[j] and loads[j] + reals(mod) > BATCH_REALS_CAP:
+                bins.append([])
+                loads.append(0)
+                j = len(bins) - 1
+            bins[j].append((mod, i))
+            loads[j] += reals(mod)
+        for b in bins:
+            if b:
+                deepest = max(b, key=lambda e: e[0]["depth"])[0]
+                batches.append((deepest, sorted(i for _, i in b), s))
     return subs, batches
 
 
@@ -289,4 +319,4 @@ def sweep_cell_updates(members, nsteps: int, substeps) -> int:
 
 __all__ = ["member_model", "spectral_radius", "substeps_for", "plan", "member_depths", "batch_reals", "run_sweep",
            "amplification",
-           "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG", "SMALL_REALS", "SMALL_STREAMS"]
+           "sweep_cell_updates", "RK4_MARGIN", "GROWTH_FLAG", "SMALL_REALS", "SMALL_STREAMS", "BATCH_REALS_CAP"]
