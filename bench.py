@@ -484,7 +484,8 @@ def optional_leg(fn, *a):
 def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False, small_streams: int = -1):
     """Wall time of the uneven batched sweep: plan (spectral radius and
     substeps per member, reported apart), then all members as batches of
-    like-shaped members: the large batches `streams` at a time, then the
+    one grid, state count and substep count (sweep.plan; mixed depths): the
+    large batches `streams` at a time, then the
     small ones `small_streams` at a time (sweep.SMALL_STREAMS if negative),
     FP32 state, R1 every step.  fp64_check: run the sweep again with the FP64
     state (untimed) and report the largest error of the FP32 absorption

@@ -1,11 +1,13 @@
 """Uneven batched sweeps: many independent propagations with different grids,
-depths, state counts and baths, run as batches of like-shaped members.
+depths, state counts and baths, run as batches of members of one grid.
 
 The linear-absorption protocol of Sec. III (thermal state, impulsive mu^x,
 R1(t) = (i/hbar) Tr{mu W^(0)(t)}, Eq. (R1)) is run for every member.
-Members that share a grid, a depth, a state count and a number of RK4
-substeps form one batch (one library handle, one launch per stage and
-member group, with the stage variant picked by qhfpe_autotune).  The large
+Members that share a grid, a state count and a number of RK4 substeps share
+batches whatever their depths (one library handle per batch, each member at
+its own depth, one launch per stage and member group, with the stage
+variant picked by qhfpe_autotune); a shape's members fill as few batches as
+keep the three FP32 state arrays of each within the memory-side cache.  The large
 batches run one after another: a tuned batch fills the GPU, and running
 several at once (each on its own stream from its own host thread; the
 library calls release the interpreter lock) was slower.  The small batches

@@ -53,3 +53,34 @@ def test_batch_size_rule():
     assert sweep.batch_reals((mod, [0], 3)) < sweep.SMALL_REALS
     big = sweep.member_model(dict(grid=256, depth=10, n_states=2, zeta=1.0, gamma=1.0, beta=1.0), 0.002)
     assert sweep.batch_reals((big, list(range(12)), 1)) >= sweep.SMALL_REALS
+
+
+def test_plan_packs_depths_into_cache_sized_batches(monkeypatch):
+    """The batching of sweep.plan, with the spectral-radius probe replaced
+    (every member one substep): members of one grid and state count share
+    batches whatever their depths, every member appears once, each batch's
+    model has its deepest member's depth, and no batch exceeds the cap
+    unless a single member does."""
+    import numpy as np
+    w = inputs.UNEVEN_SWEEP
+    members = inputs.uneven_sweep_members(w["n_members"], w["seed"])
+    monkeypatch.setattr(sweep, "spectral_radius", lambda mod, baths, **kw: np.zeros(len(baths)))
+    subs, batches = sweep.plan(members, w["dt"])
+    assert list(subs) == [1] * len(members)
+    seen = sorted(i for _, ids, _ in batches for i in ids)
+    assert seen == list(range(len(members)))
+    for mod, ids, s in batches:
+        assert s == 1
+        assert {(members[i]["grid"], members[i]["n_states"]) for i in ids} == {(mod["nq"], mod["n_states"])}
+        assert mod["depth"] == max(members[i]["depth"] for i in ids)
+        assert sweep.batch_reals((mod, ids, s), members) <= sweep.BATCH_REALS_CAP or len(ids) == 1
+    # one shape's batches are filled evenly: none below half of its largest
+    by_shape = {}
+    for mod, ids, s in batches:
+        by_shape.setdefault((mod["nq"], mod["n_states"]), []).append(sweep.batch_reals((mod, ids, s), members))
+    for sizes in by_shape.values():
+        assert min(sizes) >= 0.5 * max(sizes)
+    # one batch per shape and depth without merging
+    _, plain = sweep.plan(members, w["dt"], merge_depths=False)
+    assert all(len({members[i]["depth"] for i in ids}) == 1 for _, ids, _ in plain)
+    assert len(plain) > len(batches)
