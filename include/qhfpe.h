@@ -292,6 +292,8 @@ int qhfpe_relax(qhfpe_t* h, double tol, int64_t max_steps, int32_t check_every,
  * handle, so a copy with another phase than dst's must cover all of dst's
  * members unless dst holds no state yet (created and never loaded by
  * qhfpe_set_state, qhfpe_init_thermal or a copy): QHFPE_ESTATE otherwise.
+ * Each copied member must have the same depth in both handles
+ * (qhfpe_set_member_depth; QHFPE_ESTATE otherwise).
  * Within one handle the two ranges must not overlap (QHFPE_EINVAL).  The
  * copy is a kernel on dst's stream; when the handles' streams differ it
  * waits for src's pending work and src's later work waits for it (events

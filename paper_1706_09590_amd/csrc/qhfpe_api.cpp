@@ -1188,6 +1188,12 @@ int qhfpe_copy_members(const qhfpe_t* src, int32_t src_member, qhfpe_t* dst, int
   if (src == dst && src_member < dst_member + count && dst_member < src_member + count && src_member != dst_member)
     return fail(QHFPE_EINVAL, "overlapping member ranges within one handle");
   if (count == 0 || (src == dst && src_member == dst_member)) return QHFPE_OK;
+  // a member's levels above its own depth are never updated: copied members
+  // must keep their depths
+  for (int k = 0; k < count; ++k)
+    if (src->mdepth[src_member + k] != dst->mdepth[dst_member + k])
+      return fail(QHFPE_ESTATE, "member %d (depth %d) copied onto member %d of depth %d", src_member + k,
+                  src->mdepth[src_member + k], dst_member + k, dst->mdepth[dst_member + k]);
   // the phase i^k is one per handle: a partial copy into a loaded handle of
   // another phase would leave its other members read with the wrong phase
   const bool whole = dst_member == 0 && count == dst->p.batch;

@@ -147,6 +147,16 @@ def test_member_depth_arguments():
                 P.set_member_depth(member, depth)
             assert e.value.code == qhfpe.EINVAL
         P.set_member_depth(1, 0)
+        Q = qhfpe.Propagator(d, batch=2, precision="fp64")
+        try:
+            # copied members keep their depths
+            with pytest.raises(qhfpe.QHFPEError) as e:
+                Q.copy_members_from(P, 1, 0, 1)
+            assert e.value.code == qhfpe.ESTATE
+            Q.set_member_depth(0, 0)
+            Q.copy_members_from(P, 1, 0, 1)
+        finally:
+            Q.close()
         P.set_member_depth(1, 3)  # back to the handle's depth
     finally:
         P.close()
