@@ -327,8 +327,9 @@ enum {
  *   yy = sum_x sum_co Y_co(x)^2,
  * stored in that order (X of level `level`, Y the packed level + 1; zero
  * outside the q grid, periodic in p).  The caller zeroes d_stats
- * (QHFPE_CLOSURE_STATS_DOUBLES) before the first call.  0 <= level < depth.
- * Asynchronous. */
+ * (QHFPE_CLOSURE_STATS_DOUBLES) before the first call.  0 <= level < depth
+ * (QHFPE_EINVAL), and every member must have level + 1
+ * (qhfpe_set_member_depth; QHFPE_EUNSUPPORTED).  Asynchronous. */
 int qhfpe_closure_stats(qhfpe_t* h, int32_t level, double* d_stats);
 
 /* The kernel K whose closure is Eq. (GMFP), W^(N+1) = zeta p W^(N) +

@@ -1269,6 +1269,9 @@ int qhfpe_closure_stats(qhfpe_t* h, int32_t level, double* d_stats) {
   if (!wave_supported(h->ns, h->p.np))
     return fail(QHFPE_EUNSUPPORTED, "closure statistics need two states and np = 128 or 256");
   if (level < 0 || level >= h->p.depth) return fail(QHFPE_EINVAL, "need 0 <= level < depth (level + 1 is the target)");
+  for (int b = 0; b < h->p.batch; ++b)
+    if (h->mdepth[b] <= level)
+      return fail(QHFPE_EUNSUPPORTED, "member %d (depth %d) has no level %d", b, h->mdepth[b], level + 1);
   HIP_TRY(launch_closure_stats(h->p.precision, h->p.np, h->y(), level, h->L.member_elems, h->L.level_elems,
                                h->L.comp_elems, h->p.nq, h->p.batch, h->p.p_min, h->dp, d_stats, h->stream));
   return QHFPE_OK;
