@@ -157,6 +157,11 @@ def test_member_depth_arguments():
             Q.copy_members_from(P, 1, 0, 1)
         finally:
             Q.close()
+        # training pairs (0, 1) need level 1 in every member
+        stats = torch.zeros(qhfpe.CLOSURE_STATS_DOUBLES, dtype=torch.float64, device="cuda")
+        with pytest.raises(qhfpe.QHFPEError) as e:
+            P.closure_stats(0, stats)
+        assert e.value.code == qhfpe.EUNSUPPORTED
         P.set_member_depth(1, 3)  # back to the handle's depth
     finally:
         P.close()
