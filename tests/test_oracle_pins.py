@@ -317,6 +317,30 @@ def test_brute_force_dense_operator_matches_rhs(tiny_dense):
         assert np.linalg.norm(lhs - ref) / np.linalg.norm(ref) < 1e-13
 
 
+_TINY3 = dict(n_states=3, nq=4, np=8, q_min=-2.0, q_max=2.5, p_min=-3.0, p_max=3.0,
+              depth=1, zeta=0.6, gamma=1.1, beta=0.9, dt=0.01,
+              poly=[[[0.1, 0.2, 0.5, -0.05, 0.03], [0.3, 0.1, 0.02, 0, 0], [0.15, -0.05, 0.01, 0, 0]],
+                    [[0.3, 0.1, 0.02, 0, 0], [2.0, -0.4, 0.6, 0.01, 0.02], [0.2, 0.08, -0.015, 0, 0]],
+                    [[0.15, -0.05, 0.01, 0, 0], [0.2, 0.08, -0.015, 0, 0], [1.0, 0.3, 0.4, 0.0, 0.01]]],
+              mu=[[0.1, 1.0, 0.4], [1.0, -0.2, 0.7], [0.4, 0.7, 0.3]], mass=1.0, hbar=1.0,
+              low_temp_correction=True)
+
+
+def test_brute_force_dense_operator_three_states_with_q_dependent_couplings():
+    """Three states with a different quadratic coupling on every pair (all
+    of them q-dependent, so the r-space term mixes every block): the
+    oracle's RHS against the dense operator built from explicit sums."""
+    L = _dense_operator(_TINY3)
+    m = oracle_model(_TINY3)
+    rng = np.random.default_rng(13)
+    shape = (2, 3, 3, 4, 8)
+    for _ in range(3):
+        x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        lhs = O.rhs(m, x).reshape(-1)
+        ref = L @ x.reshape(-1)
+        assert np.linalg.norm(lhs - ref) / np.linalg.norm(ref) < 1e-13
+
+
 # Morse diagonals and a Gaussian coupling (the form of Sec. III), written here
 # point by point with math.exp, independently of the oracle's vectorised
 # surfaces; parameters chosen so that every term matters on the tiny grid.
