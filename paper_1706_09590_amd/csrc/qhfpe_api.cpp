@@ -347,13 +347,14 @@ struct qhfpe_handle {
   std::vector<int> mdepth, hmlev;
   bool mixed = false;
 
+  // (teardown: a failure to release has nothing left to report to)
   ~qhfpe_handle() {
     for (int g = 0; g < groups_made; ++g) {
-      if (gstream[g]) hipStreamDestroy(gstream[g]);
-      if (gjoin[g]) hipEventDestroy(gjoin[g]);
+      if (gstream[g]) (void)hipStreamDestroy(gstream[g]);
+      if (gjoin[g]) (void)hipEventDestroy(gjoin[g]);
     }
-    if (gfork) hipEventDestroy(gfork);
-    if (xevent) hipEventDestroy(xevent);
+    if (gfork) (void)hipEventDestroy(gfork);
+    if (xevent) (void)hipEventDestroy(xevent);
   }
 
   // Default for small batches, where one launch per stage leaves most SIMDs
@@ -377,7 +378,7 @@ struct qhfpe_handle {
       hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
       if (e != hipSuccess) {
-        if (st) hipStreamDestroy(st);
+        if (st) (void)hipStreamDestroy(st);  // the creation error is the one reported
         return e;
       }
       gstream[groups_made] = st;
@@ -837,7 +838,7 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(QHFPE_EHIP, "hipEventCreate failed");
   }
   int best = h->cpt;
@@ -865,8 +866,8 @@ int qhfpe_autotune(qhfpe_t* h, int32_t reps, int32_t* h_chosen) {
       best = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);  // the events are scratch; a release failure changes no result
+  (void)hipEventDestroy(e1);
   h->cpt = best;
   if (rc == QHFPE_OK && h_chosen) *h_chosen = best;
   return rc;
@@ -1378,16 +1379,17 @@ int qhfpe_graph_end(void* stream, qhfpe_graph_t** out) {
   hipGraphExec_t x = nullptr;
   hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(QHFPE_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
   size_t nodes = 0;
-  hipGraphGetNodes(g, nullptr, &nodes);
-  qhfpe_graph_t* r = new (std::nothrow) qhfpe_graph();
+  e = hipGraphGetNodes(g, nullptr, &nodes);
+  qhfpe_graph_t* r = e == hipSuccess ? new (std::nothrow) qhfpe_graph() : nullptr;
   if (!r) {
-    hipGraphExecDestroy(x);
-    hipGraphDestroy(g);
-    return fail(QHFPE_EINVAL, "out of host memory");
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    return e != hipSuccess ? fail(QHFPE_EHIP, "hipGraphGetNodes: %s", hipGetErrorString(e))
+                           : fail(QHFPE_EINVAL, "out of host memory");
   }
   r->graph = g;
   r->exec = x;
@@ -1410,9 +1412,10 @@ int qhfpe_graph_launch(qhfpe_graph_t* g, void* stream) {
 
 int qhfpe_graph_destroy(qhfpe_graph_t* g) {
   if (!g) return QHFPE_OK;
-  hipGraphExecDestroy(g->exec);
-  hipGraphDestroy(g->graph);
+  const hipError_t a = hipGraphExecDestroy(g->exec), b = hipGraphDestroy(g->graph);
   delete g;
+  if (a != hipSuccess || b != hipSuccess)
+    return fail(QHFPE_EHIP, "destroying the graph: %s", hipGetErrorString(a != hipSuccess ? a : b));
   return QHFPE_OK;
 }
 
