@@ -199,8 +199,7 @@ double qhfpe_morse_gauss_potential(int32_t j, int32_t l, double x, void* ctx);
  * three-state).  1: the wave-independent variant, one 64-lane wave per
  * task of q columns, each lane holding np/64 consecutive p nodes: two
  * states at np = 128 or 256 (512/np columns per task); three states with
- * constant couplings at np = 128, and at np = 256 in FP32 (two columns per
- * task).  0 = default: 1 where available, else 4 (2 for three states); it
+ * constant couplings at np = 128 (two columns per task) or 256 (one).  0 = default: 1 where available, else 4 (2 for three states); it
  * is also the variant at create.  With a q-dependent coupling only tile 2
  * and, for two states, tile 1 exist (see qhfpe_set_potential).  Variants compute the same operations per
  * cell; results agree to rounding (the compiled instruction order and the

@@ -63,22 +63,22 @@ constexpr int kWaveSmallTasks = 2048;
 inline bool wave_supported(int ns, int np) { return ns == 2 && (np == 128 || np == 256); }
 // q columns per task of the wave variant (a lane holds np / 64 p nodes)
 constexpr int wave_columns(int np) { return 512 / np; }
-// The three-state wave variant (stage_wave3.hpp): two q columns per task,
-// np = 128 or 256 in FP32 and np = 128 in FP64 (an FP64 task at np = 256
-// would need 40 KB of LDS), constant couplings only, six multiplier planes.
-constexpr int kWave3Columns = 2;
+// The three-state wave variant (stage_wave3.hpp): np = 128 or 256, constant
+// couplings only, six multiplier planes; two q columns per task at np = 128,
+// one at np = 256 (LDS: 11 KB per FP32 wave instead of 20).
+constexpr int wave3_columns(int np) { return np == 256 ? 1 : 2; }
 constexpr int kWaveTables3 = 6;
-inline bool wave3_supported(int elem_bytes, int np) { return np == 128 || (np == 256 && elem_bytes == 4); }
+inline bool wave3_supported(int /*elem_bytes*/, int np) { return np == 128 || np == 256; }
 inline bool wave_variant_supported(int elem_bytes, int ns, int np) {
   return ns == 2 ? wave_supported(ns, np) : wave3_supported(elem_bytes, np);
 }
-inline int wave_columns_of(int ns, int np) { return ns == 3 ? kWave3Columns : wave_columns(np); }
+inline int wave_columns_of(int ns, int np) { return ns == 3 ? wave3_columns(np) : wave_columns(np); }
 inline int wave_table_planes(int ns) { return ns == 3 ? kWaveTables3 : kWaveTables; }
 // Waves per workgroup of a three-state wave launch of `tasks` tasks: four
-// only for large FP32 launches at np = 128 (elsewhere a four-wave group's
-// LDS would leave room for one group per CU).
-inline int wave3_wpb(int elem_bytes, int np, long long tasks) {
-  return (elem_bytes == 4 && np == 128 && tasks > kWaveSmallTasks) ? kWaveTasksPerBlock : kWaveTasksPerBlockSmall;
+// only for large FP32 launches (an FP64 four-wave group's LDS would leave
+// room for one group per CU).
+inline int wave3_wpb(int elem_bytes, int /*np*/, long long tasks) {
+  return (elem_bytes == 4 && tasks > kWaveSmallTasks) ? kWaveTasksPerBlock : kWaveTasksPerBlockSmall;
 }
 inline bool tile_supported(int elem_bytes, int ns, int np, int code) {
   return code == kTileWave ? wave_variant_supported(elem_bytes, ns, np) : cpt_supported(elem_bytes, ns, code);

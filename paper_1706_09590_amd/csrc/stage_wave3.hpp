@@ -2,32 +2,33 @@
 // out = y + coef * L v with the operator of stage_kernel.hpp (Eq. (heom) of
 // Ikeda & Tanimura (2017) with one Drude exponential and V(q) = q, closed by
 // Eq. (GMFP); potential term of Eq. (quantum-liouvillian) through the DFT
-// along p; Sec. III discretisation), for np = 128 or 256 in FP32 and
-// np = 128 in FP64.
+// along p; Sec. III discretisation), for np = 128 or 256.
 //
 // The plan of the two-state wave variant (stage_wave.hpp), widened to the
-// nine packed components of three states.  One wave owns a task: two
-// neighbouring q columns of one level of one batch member.  Lane l holds the
-// K = np / 64 consecutive p nodes K l .. K l + K - 1 of both columns.  The
-// waves of a workgroup share only the twiddle and symbol tables.
+// nine packed components of three states.  One wave owns a task: C
+// neighbouring q columns of one level of one batch member (C = 2 at
+// np = 128, 1 at np = 256).  Lane l holds the K = np / 64 consecutive p
+// nodes K l .. K l + K - 1 of every column.  The waves of a workgroup share
+// only the twiddle and symbol tables.
 //
 //  - local terms (kinetic, level couplings, terminator) one component at a
 //    time, exactly as for two states; the constant couplings -(i/hbar)
 //    [Delta, W] afterwards, from this lane's own LDS entries of all nine
 //    components;
-//  - potential term: nine complex np-point transforms per task, four per
-//    column (the diagonal pair W00 + i W11 and the coherences W01, W02,
-//    W12) and one for the two columns' W22 (W22 of the first column + i
-//    W22 of the second).  The transform count is not a multiple of the
+//  - potential term: four complex np-point transforms per column (the
+//    diagonal pair W00 + i W11 and the coherences W01, W02, W12) and one for
+//    W22 (W22 of the first column + i W22 of the second; with one column
+//    per task, + i times a zero column).  The transform count is not a multiple of the
 //    wave's width, so each FFT pass runs in rounds of 64 items (the last one
 //    partly idle); in the contiguous passes a round holds four whole
 //    transforms, so the partner row -m of every row of a round lies in the
 //    same round and the r-space multiply runs round by round in place.
 //
-// LDS per wave: the 18 real columns of the task (19.9 KB in FP32 at
-// np = 256), so a CU holds six such waves (two-wave workgroups); at np = 128
-// FP32 holds three waves per SIMD.  FP64 at np = 256 would need 40 KB per
-// wave and is left to the workgroup variant.
+// LDS per wave: the real columns of the task's transforms (18 at np = 128,
+// 10.6 KB in FP32; 10 at np = 256, 11 KB in FP32).  Two columns per task at
+// np = 256 would need 19.9 KB per FP32 wave (six waves per CU) and 40 KB per
+// FP64 one; one column holds twelve FP32 waves per CU, at the price of a
+// half-empty W22 transform and a 7-column window for one output column.
 #pragma once
 
 #include "stage_wave.hpp"
@@ -39,9 +40,9 @@ struct WavePlan3 {
   static constexpr int NP = NP_;
   static constexpr int N1 = FftSplit<NP>::N1, N2 = FftSplit<NP>::N2;
   static constexpr int K = NP / 64;       // p nodes per lane
-  static constexpr int C = kWave3Columns;  // q columns per task
+  static constexpr int C = wave3_columns(NP);  // q columns per task
   static constexpr int NC = 9;            // packed components (three states)
-  static constexpr int NF = 4 * C + C / 2;  // complex transforms per task
+  static constexpr int NF = 4 * C + (C + 1) / 2;  // complex transforms per task
   static constexpr int P1 = NF * N2;      // items of the stride-N2 passes
   static constexpr int P2 = NF * N1;      // items of the contiguous passes
   static constexpr int R1 = (P1 + 63) / 64, R2 = (P2 + 63) / 64;  // rounds of 64 items
@@ -49,22 +50,24 @@ struct WavePlan3 {
   static constexpr int NT = 64 * WPB;
   static constexpr int LDP0 = NP + NP / N2;
   static constexpr int LDP = LDP0 + ((4 - LDP0 % 16) + 16) % 16;
-  static_assert(C == 2 && K >= 2 && 64 % N1 == 0 && N2 % 4 == 0, "three-state wave plan");
+  static_assert((C == 1 || C == 2) && K >= 2 && 64 % N1 == 0 && N2 % 4 == 0, "three-state wave plan");
 };
 
-// LDS column of packed component comp of task column i: transform f = 4 i + t
-// takes columns 2 f (real part) and 2 f + 1 (imaginary part): t = 0 the
-// diagonal pair (W00, W11), t = 1..3 the coherence (Re, Im) of the pairs
-// (0,1), (0,2), (1,2); transform 8 takes W22 of columns 0 and 1.
+// LDS column of packed component comp of task column i (C columns per
+// task): transform f = 4 i + t takes columns 2 f (real part) and 2 f + 1
+// (imaginary part): t = 0 the diagonal pair (W00, W11), t = 1..3 the
+// coherence (Re, Im) of the pairs (0,1), (0,2), (1,2); transform 4 C takes
+// W22 of columns 0 and 1 (with C = 1, column 8 C + 1 holds zeros).
+template <int C>
 __device__ __forceinline__ constexpr int wave3_slot(int i, int comp) {
-  return comp < 2 ? 8 * i + comp : (comp == 2 ? 16 + i : 8 * i + comp - 1);
+  return comp < 2 ? 8 * i + comp : (comp == 2 ? 8 * C + i : 8 * i + comp - 1);
 }
 
 // Waves per SIMD the register allocation aims at (the second launch bound):
-// three for FP32 at np = 128, two otherwise (LDS allows no more).
+// three in FP32, two in FP64 (LDS allows no more).
 template <typename T, int NP>
 constexpr int wave3_waves_per_simd() {
-  return (sizeof(T) == 4 && NP == 128) ? 3 : 2;
+  return sizeof(T) == 4 ? 3 : 2;
 }
 
 // NTS: non-temporal output stores (StageArgs::stream_out).  WPB: waves per
@@ -247,7 +250,8 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
         //   n < N: v^(n+1) + n gamma c0 v^(n-1);  n = N: zeta p v^(N) + N gamma c0 v^(N-1)
         g[j] = lw[ls][0][i][j] + (zterm * p[j]) * w0 + (ng * c0) * lw[ls][1][i][j];
         lev[j] = -ng * w0 + (ng * zeta * p[j]) * lw[ls][1][i][j];
-        s[wave3_slot(i, comp) * LDP + pad(a0 + j)] = w0;
+        s[wave3_slot<C>(i, comp) * LDP + pad(a0 + j)] = w0;
+        if (C == 1 && comp == 2) s[(8 * C + 1) * LDP + pad(a0 + j)] = T(0);  // imaginary part of the W22 transform
       }
       // D_p g with the neighbouring lanes' nodes (periodic in p)
       T e[K + 4];
@@ -291,7 +295,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
       for (int j = 0; j < K; ++j) {
         T hv[NC], cm[NC];
 #pragma unroll
-        for (int comp = 0; comp < NC; ++comp) hv[comp] = s[wave3_slot(i, comp) * LDP + pad(a0 + j)];
+        for (int comp = 0; comp < NC; ++comp) hv[comp] = s[wave3_slot<C>(i, comp) * LDP + pad(a0 + j)];
         commutator_mi<3, T>(cpl, hv, cm);
 #pragma unroll
         for (int comp = 0; comp < NC; ++comp) base[i][comp][j] += coef * cm[comp];
@@ -336,7 +340,9 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
   // of states 0..2, 3..5 the coherence tables of the pairs (0,1), (0,2),
   // (1,2) halved (a coherence is treated as a pair of equal multipliers).
   // The packed diagonals take planes 0 and 1 at their column; the W22
-  // transform takes plane 2 at column q0 (real part) and q0 + 1 (imaginary).
+  // transform takes plane 2 at column q0 (real part) and q0 + 1 (imaginary;
+  // with one column per task its multiplier meets a zero column and does
+  // not matter).
   const unsigned tbytes = (unsigned)((long long)nq * NP * ES);
   const rsrc_t rt = make_rsrc(a.mtab, (unsigned)kWaveTables3 * tbytes);
   auto load_mul = [&](int t, T* mA, T* mB) {
@@ -471,7 +477,7 @@ __global__ void __launch_bounds__((WavePlan3<NP, WPB_>::NT), (wave3_waves_per_si
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) o[comp][j] = base[i][comp][j] + coef * s[wave3_slot(i, comp) * LDP + pad(a0 + j)];
+      for (int j = 0; j < K; ++j) o[comp][j] = base[i][comp][j] + coef * s[wave3_slot<C>(i, comp) * LDP + pad(a0 + j)];
       buf_store_n<K, NTS ? kStoreNT : 0>(o[comp], ro, qo[i + 3], comp * cbytes);
     }
     if (want_trace) {
@@ -500,16 +506,15 @@ hipError_t launch_wave3_one(const StageArgs& a, int nblocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-// workgroup sizes: four waves only for FP32 at np = 128 (large launches);
-// two elsewhere (a four-wave FP32 np = 256 workgroup needs 84 KB of LDS, so
-// one would fit per CU)
+// workgroup sizes: four waves only in FP32 (large launches); two in FP64
+// (a four-wave FP64 workgroup's LDS would leave room for one per CU)
 template <typename T, int NP>
 hipError_t launch_wave3_np(const StageArgs& a, int nblocks, hipStream_t s) {
   if (a.closure != nullptr || a.qcoup) return hipErrorInvalidValue;
   if (a.wpb == kWaveTasksPerBlockSmall)
     return a.stream_out ? launch_wave3_one<T, NP, true, kWaveTasksPerBlockSmall>(a, nblocks, s)
                         : launch_wave3_one<T, NP, false, kWaveTasksPerBlockSmall>(a, nblocks, s);
-  if constexpr (sizeof(T) == 4 && NP == 128) {
+  if constexpr (sizeof(T) == 4) {
     if (a.wpb == kWaveTasksPerBlock)
       return a.stream_out ? launch_wave3_one<T, NP, true, kWaveTasksPerBlock>(a, nblocks, s)
                           : launch_wave3_one<T, NP, false, kWaveTasksPerBlock>(a, nblocks, s);
@@ -520,9 +525,7 @@ hipError_t launch_wave3_np(const StageArgs& a, int nblocks, hipStream_t s) {
 template <typename T>
 hipError_t launch_stage_wave3(int np, const StageArgs& a, int nblocks, hipStream_t s) {
   if (np == 128) return launch_wave3_np<T, 128>(a, nblocks, s);
-  if constexpr (sizeof(T) == 4) {
-    if (np == 256) return launch_wave3_np<T, 256>(a, nblocks, s);
-  }
+  if (np == 256) return launch_wave3_np<T, 256>(a, nblocks, s);
   return hipErrorInvalidValue;
 }
 

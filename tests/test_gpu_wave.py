@@ -117,8 +117,9 @@ def test_wave_availability():
     P = qhfpe.Propagator(d, batch=1, precision="fp64")
     assert P.autotune(2) in (WAVE, 2, 4)
     P.close()
+    # (three states have their own wave variant: test_gpu_wave3.py)
     for bad in (inputs.model_dict(d, np=64), inputs.model_dict(d, np=192), inputs.model_dict(
-            d, n_states=3, poly=inputs.three_state_surfaces(0.3, 0.2), mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])):
+            d, np=192, n_states=3, poly=inputs.three_state_surfaces(0.3, 0.2), mu=[[0, 1, 0], [1, 0, 0], [0, 0, 0]])):
         P = qhfpe.Propagator(bad, batch=1, precision="fp64")
         with pytest.raises(qhfpe.QHFPEError):
             P.set_tile(WAVE)

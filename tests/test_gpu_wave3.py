@@ -1,6 +1,6 @@
 """Parity of the three-state wave variant (tile code 1 with three states: one
-wave per two q columns; np = 128 or 256 in FP32, np = 128 in FP64) with the
-FP64 oracle and with the workgroup variant.
+wave per two q columns at np = 128, per column at np = 256) with the FP64
+oracle and with the workgroup variant.
 
 Bars as in test_gpu_wave.py: FP64 relative L2 <= 1e-12 per operator
 application, variants agree to 1e-13 (FP64) / 1e-5 (FP32) after
@@ -68,13 +68,14 @@ def rhs_case(d, precision, seed, phase, smooth=True):
 
 @pytest.mark.parametrize("nq,depth", [(13, 2), (8, 0), (48, 1), (9, 3), (5, 1)])
 @pytest.mark.parametrize("phase", [0, 1])
-def test_wave3_rhs_parity(nq, depth, phase):
-    """FP64 at np = 128: ragged q (an odd nq leaves the last task one
-    column past the edge, so its W22 transform pairs a column with zeros),
-    the terminator at depth 0, five columns (three tasks, the last half
-    past the edge)."""
-    say(f"wave3 rhs np=128 nq={nq} depth={depth} phase={phase}")
-    err = rhs_case(model(nq=nq, depth=depth), "fp64", seed=700 + nq + depth + phase, phase=phase)
+@pytest.mark.parametrize("np_", [128, 256])
+def test_wave3_rhs_parity(nq, depth, phase, np_):
+    """FP64: ragged q at np = 128 (an odd nq leaves the last task one column
+    past the edge, so its W22 transform pairs a column with zeros), one
+    column per task at np = 256 (W22 paired with a zero column), the
+    terminator at depth 0."""
+    say(f"wave3 rhs np={np_} nq={nq} depth={depth} phase={phase}")
+    err = rhs_case(model(nq=nq, depth=depth, np_=np_), "fp64", seed=700 + nq + depth + phase + np_, phase=phase)
     assert err < 1e-12, err
 
 
@@ -101,7 +102,7 @@ def test_wave3_rhs_parity_fp32(np_):
     assert rhs_case(model(nq=6, depth=0, np_=np_), "fp32", seed=75 + np_, phase=1, smooth=False) < 1e-5
 
 
-@pytest.mark.parametrize("precision,np_", [("fp64", 128), ("fp32", 128), ("fp32", 256)])
+@pytest.mark.parametrize("precision,np_", [("fp64", 128), ("fp64", 256), ("fp32", 128), ("fp32", 256)])
 def test_wave3_agrees_with_workgroup_variant(precision, np_):
     """Propagation with two members of different baths, traces every 3
     steps (the trace partials of the wave kernel against the workgroup
@@ -145,12 +146,12 @@ def test_wave3_large_launch_and_groups_bitwise():
 
 def test_wave3_availability():
     ok = model(nq=16, depth=1)
-    for prec, np_ in (("fp64", 128), ("fp32", 128), ("fp32", 256)):
+    for prec, np_ in (("fp64", 128), ("fp64", 256), ("fp32", 128), ("fp32", 256)):
         P = qhfpe.Propagator(inputs.model_dict(ok, np=np_), batch=1, precision=prec)
         P.set_tile(WAVE)
         assert P.autotune(2) in (WAVE, 2, 4)
         P.close()
-    for prec, np_ in (("fp64", 256), ("fp32", 192), ("fp64", 64)):
+    for prec, np_ in (("fp64", 192), ("fp32", 192), ("fp64", 64)):
         P = qhfpe.Propagator(inputs.model_dict(ok, np=np_), batch=1, precision=prec)
         with pytest.raises(qhfpe.QHFPEError):
             P.set_tile(WAVE)
