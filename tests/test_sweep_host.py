@@ -84,3 +84,13 @@ def test_plan_packs_depths_into_cache_sized_batches(monkeypatch):
     _, plain = sweep.plan(members, w["dt"], merge_depths=False)
     assert all(len({members[i]["depth"] for i in ids}) == 1 for _, ids, _ in plain)
     assert len(plain) > len(batches)
+
+
+def test_batch_size_counts_each_members_own_levels():
+    mod = sweep.member_model(dict(grid=128, depth=10, n_states=3, zeta=1.0, gamma=1.0, beta=1.0), 0.002)
+    members = [dict(grid=128, depth=d, n_states=3) for d in (10, 4, 0)]
+    batch = (mod, [0, 1, 2], 1)
+    assert sweep.member_depths(batch, members) == [10, 4, 0]
+    assert sweep.member_depths(batch) == [10, 10, 10]
+    assert sweep.batch_reals(batch, members) == (11 + 5 + 1) * 128 * 128 * 9
+    assert sweep.batch_reals(batch) == 3 * 11 * 128 * 128 * 9
