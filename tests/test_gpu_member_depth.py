@@ -165,3 +165,42 @@ def test_member_depth_arguments():
         P.set_member_depth(1, 3)  # back to the handle's depth
     finally:
         P.close()
+
+
+@pytest.mark.parametrize("np_,tile", [(64, 2), (128, 1)])
+def test_mixed_depths_with_a_q_dependent_coupling(np_, tile):
+    """Members of depths 3 and 1 with the Morse/Gaussian surfaces (the
+    r-space coupling path of the workgroup and wave variants): each equals
+    a handle of its own depth bit for bit."""
+    say(f"member depths with q-dependent coupling np={np_} tile={tile}")
+    mg = dict(D0=3.0, D1=2.5, a0=0.4, a1=0.5, q0=-0.3, q1=0.8, dE=0.7, dV=0.45, qs=0.4, sigma=0.9)
+    depths = [3, 1]
+    d = model(2, np_, 14, 3)
+    P = qhfpe.Propagator(d, batch=2, precision="fp64")
+    try:
+        P.set_potential_morse_gauss(**mg)
+        for b, dep in enumerate(depths):
+            P.set_member_bath(b, *BATHS[b])
+            if dep != 3:
+                P.set_member_depth(b, dep)
+        P.set_tile(tile)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        tr = P.step(6, 2).cpu().numpy()
+        st = P.get_state().cpu().numpy()
+    finally:
+        P.close()
+    for b, dep in enumerate(depths):
+        Q = qhfpe.Propagator(model(2, np_, 14, dep), batch=1, precision="fp64")
+        try:
+            Q.set_potential_morse_gauss(**mg)
+            Q.set_member_bath(0, *BATHS[b])
+            Q.set_tile(tile)
+            Q.init_thermal(1.0)
+            Q.apply_dipole()
+            tr1 = Q.step(6, 2).cpu().numpy()
+            st1 = Q.get_state().cpu().numpy()
+        finally:
+            Q.close()
+        np.testing.assert_array_equal(tr[b], tr1[0])
+        np.testing.assert_array_equal(st[b, :dep + 1], st1[0])
