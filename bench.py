@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's own model (Morse/Gaussian surfaces, 128 x 512, depth 5)")
     ap.add_argument("--paper-steps", type=int, default=0, help="RK4 steps of the paper workload (0: its own)")
+    ap.add_argument("--three-state", action="store_true",
+                    help="also time stage passes of a three-state 256x256 depth-8 batch of four members (FP32)")
     ap.add_argument("--closure", action="store_true",
                     help="also train the learned terminator on depth-10 runs of the 2D protocol and compare the "
                          "depth-3 + closure 2D spectra with plain depth 3 and plain depth 10")
@@ -371,6 +373,8 @@ def main():
                                             args.sweep_small_streams)
     if args.paper:
         line["paper_workload"] = optional_leg(paper_workload, args.paper_steps)
+    if args.three_state:
+        line["three_state_batch"] = optional_leg(three_state_batch)
     if args.closure:
         line["learned_closure"] = optional_leg(learned_closure)
     if args.closure_depths:
@@ -544,6 +548,41 @@ def uneven_sweep(nsteps: int = 0, streams: int = 1, fp64_check: bool = False, sm
         out["growing_members_min_zeta"] = float(min(members[i]["zeta"] for i in np.flatnonzero(grow))) if grow.any() else None
         out["growing_members_min_depth"] = int(min(members[i]["depth"] for i in np.flatnonzero(grow))) if grow.any() else None
     return out
+
+
+def three_state_batch(nsteps: int = 100):
+    """Stage passes of a three-state batch: 256x256, depth 8, four members of
+    different baths, FP32 state, the default (wave) variant and member
+    grouping, nsteps RK4 steps after 10 warm-up steps, HIP events on the
+    handle's stream; bytes on the 12-pass convention (3 n_s^2 w per cell,
+    member and stage pass)."""
+    import torch
+
+    from paper_1706_09590_amd import qhfpe, sweep
+    m = sweep.member_model(dict(grid=256, depth=8, n_states=3, zeta=0.5, gamma=1.0, beta=1.0), 0.002)
+    B = 4
+    P = qhfpe.Propagator(m, batch=B, precision="fp32")
+    try:
+        for b, (z, g, beta) in enumerate([(0.3, 1.0, 1.0), (0.6, 0.8, 1.2), (0.9, 1.1, 0.9), (0.45, 0.7, 1.0)]):
+            P.set_member_bath(b, z, g, beta)
+        P.init_thermal(1.0)
+        P.apply_dipole()
+        P.step(10, 1, record=False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        P.step(nsteps, 1, record=False)
+        e1.record(P.stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / (4 * nsteps)
+    finally:
+        P.close()
+    cells = B * (m["depth"] + 1) * m["nq"] * m["np"]
+    bytes_pass = 3 * 9 * 4 * cells
+    return dict(grid=256, depth=8, members=B, n_states=3, precision="fp32", rk4_steps=nsteps,
+                stage_pass_us=us, cell_updates_per_s=cells * 1e6 / (4 * us),
+                achieved_gbs_12pass=bytes_pass / (us * 1e3))
 
 
 def paper_workload(nsteps: int = 0):
