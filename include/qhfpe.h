@@ -23,7 +23,8 @@
  *  - Work is enqueued on the handle's stream (qhfpe_step's member groups
  *    run on their own streams between an event fork and join on it).
  *    qhfpe_create, qhfpe_set_state, qhfpe_set_member_bath,
- *    qhfpe_set_potential, qhfpe_autotune, qhfpe_step, qhfpe_status,
+ *    qhfpe_set_member_depth, qhfpe_set_potential,
+ *    qhfpe_set_potential_tables, qhfpe_autotune, qhfpe_step, qhfpe_status,
  *    qhfpe_residual and qhfpe_relax synchronise that stream before they
  *    return (they upload tables or read a result or a status flag back);
  *    the other calls are asynchronous.  Only asynchronous calls may be
